@@ -1,0 +1,167 @@
+"""Pins of the oracle's PCAL iteration (Section 3.3) against brute force,
+closed forms and invariants."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as wl
+from oracle import fem, pcal
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = wl.make_workload("c1")
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    return w, d, prob, X0
+
+
+def test_c1_dense_eigenvalues_golden(c1):
+    """The stored dense eigenvalues (written by tests/golden/make_golden.py from
+    the oracle's matrices and LAPACK) still describe the oracle's matrices."""
+    w, d, prob, _ = c1
+    g = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))
+    ev = sla.eigh(d.csr(d.H).toarray(), d.csr(d.B).toarray(), eigvals_only=True,
+                  subset_by_index=[0, 7])
+    assert np.allclose(ev, g["eigenvalues"], rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("precond", ["none", "paper"])
+def test_pcal_converges_to_dense_generalized_eigenvalues(c1, precond):
+    """Linear problem: PCAL + Rayleigh-Ritz reaches the p smallest eigenpairs of
+    (H, B) computed by a dense LAPACK solve (post-processing, Section 4.3)."""
+    w, d, prob, X0 = c1
+    X, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-10, max_iter=2000,
+                                              precond=precond))
+    assert hist[-1].rel < 1e-10
+    lam, Xr = pcal.rayleigh_ritz(prob, X)
+    g = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))
+    ref = np.array(g["eigenvalues"][: w.p])
+    assert np.allclose(lam, ref, rtol=1e-10, atol=0)
+    # feasibility reached without any orthogonalization inside the loop
+    assert hist[-1].fea < 1e-9
+    # Rayleigh-Ritz does not change the energy (Section 4.3) and diagonalizes
+    S = Xr.T @ prob.bx(Xr)
+    L0 = Xr.T @ prob.hx(Xr)
+    assert np.allclose(S, np.eye(w.p), atol=1e-9)
+    assert np.allclose(L0, np.diag(lam), atol=1e-9)
+    assert abs(np.trace(L0) - hist[-1].energy) < 1e-9 * abs(hist[-1].energy)
+
+
+def test_ky_fan_bound_holds_at_every_iterate(c1):
+    """tr(S^{-1} Lambda0) >= sum of the p smallest eigenvalues for any full-rank X."""
+    w, d, prob, X0 = c1
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-9, max_iter=2000))
+    g = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))
+    lower = float(np.sum(g["eigenvalues"][: w.p]))
+    E = np.array([h.energy for h in hist])
+    assert np.all(E >= lower - 1e-12 * abs(lower))
+    assert abs(E[-1] - lower) < 1e-9 * abs(lower)
+
+
+def test_single_column_stays_feasible_to_machine_precision(c1):
+    """p = 1: the column normalization is the B-orthonormalization, so fea is at
+    rounding level at every iterate (Section 5.1, the He case)."""
+    w, d, prob, _ = c1
+    X0 = pcal.chol_gs(prob, wl.random_block(5, d.n, 1))
+    X, hist = pcal.pcal(prob, X0, pcal.Params(beta=1.0, tol=1e-10, max_iter=1000, precond="paper"))
+    assert max(h.fea for h in hist) < 1e-14
+    assert abs(hist[-1].energy - json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))
+               ["eigenvalues"][0]) < 1e-10
+
+
+def test_chol_gs_gives_b_orthonormal_start(c1):
+    w, d, prob, X0 = c1
+    S = X0.T @ prob.bx(X0)
+    assert np.abs(S - np.eye(w.p)).max() < 1e-13
+    # same column space as V (X0 = V R^{-1})
+    V = wl.random_block(0, d.n, w.p)
+    coef = np.linalg.lstsq(V, X0, rcond=None)[0]
+    assert np.abs(V @ coef - X0).max() < 1e-10
+
+
+def test_multiplier_correction_vanishes_at_feasibility():
+    """eq. lambda2: at X^T B X = I the Theta term is zero and Lambda = X^T H X
+    (eq. closed-multi); away from it only the diagonal moves."""
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((6, 6))
+    L0 = A + A.T
+    assert np.array_equal(pcal.multiplier(np.eye(6), L0, 3.0), L0)
+    E = rng.standard_normal((6, 6)) * 1e-2
+    S = np.eye(6) + E + E.T
+    Lam = pcal.multiplier(S, L0, 3.0)
+    off = ~np.eye(6, dtype=bool)
+    assert np.array_equal(Lam[off], L0[off])
+    # the diagonal equals diag(X^T grad L_beta) computed from the full matrices
+    want = np.diag(L0 - S @ L0 + 3.0 * S @ (S - np.eye(6)))
+    assert np.allclose(np.diag(Lam) - np.diag(L0), want, rtol=1e-14, atol=1e-15)
+
+
+def test_gradient_matches_finite_differences_of_the_augmented_lagrangian(c1):
+    """G = H X - B X Lambda + beta B X (X^T B X - I) is the gradient of
+    L_beta(X, Lambda) = tr(X^T H X)/2 - <Lambda, X^T B X - I>/2 + beta/4 ||X^T B X - I||^2
+    (eq. prob:ALM-sub with the gradient scaled as in Section 2.2)."""
+    w, d, prob, X0 = c1
+    rng = np.random.default_rng(1)
+    X = X0 + 0.05 * rng.standard_normal(X0.shape) / np.sqrt(d.n)
+    Zd = rng.standard_normal(X0.shape)
+    A = rng.standard_normal((w.p, w.p))
+    Lam = A + A.T
+    beta = 2.5
+    I = np.eye(w.p)
+
+    def Lb(Y):
+        S = Y.T @ prob.bx(Y)
+        return 0.5 * np.sum(Y * prob.hx(Y)) - 0.5 * np.sum(Lam * (S - I)) + beta / 4 * np.sum((S - I) ** 2)
+
+    BX = prob.bx(X)
+    S = X.T @ BX
+    G = prob.hx(X) - BX @ Lam + beta * BX @ (S - I)
+    eps = 1e-5
+    fd = (Lb(X + eps * Zd) - Lb(X - eps * Zd)) / (2 * eps)
+    assert abs(fd - np.sum(G * Zd)) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_preconditioner_pcg_reaches_the_direct_solve(c1):
+    """With enough iterations the Jacobi-PCG inner solve equals the direct solve
+    of (L/2 - lambda B) x = g (eq. precondition-T)."""
+    w, d, prob, X0 = c1
+    rng = np.random.default_rng(2)
+    G = rng.standard_normal((d.n, 3))
+    lam = np.array([-1.0, -0.4, -2.5])
+    P = pcal.pcg_shifted(prob, G, lam, iters=400)
+    for l in range(3):
+        T = d.csr(0.5 * d.L - lam[l] * d.B).toarray()
+        ref = np.linalg.solve(T, G[:, l])
+        assert np.allclose(P[:, l], ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+    # identity branch for non-negative multipliers
+    lamd = np.array([-1.0, 0.0, 0.3])
+    Pm = pcal.precondition(prob, G, lamd, pcal.Params(precond="paper", pcg_iters=5))
+    assert np.array_equal(Pm[:, 1:], G[:, 1:])
+
+
+def test_energy_is_rotation_invariant(c1):
+    w, d, prob, X0 = c1
+    Q, _ = np.linalg.qr(np.random.default_rng(4).standard_normal((w.p, w.p)))
+    X = X0 + 0.1 * np.random.default_rng(5).standard_normal(X0.shape) / np.sqrt(d.n)
+
+    def E(Y):
+        S = Y.T @ prob.bx(Y)
+        return prob.energy(Y, S, Y.T @ prob.hx(Y))
+
+    assert abs(E(X) - E(X @ Q)) < 1e-12 * abs(E(X))
+
+
+def test_bb_rules_on_a_quadratic():
+    """For s, y = a s (a quadratic with curvature a) both BB rules return a."""
+    s = np.random.default_rng(0).standard_normal((50, 3))
+    for rule in ("bb1", "bb2", "abb1", "abb2"):
+        assert abs(pcal.bb_eta(rule, 3, s, 7.5 * s, 1.0, 1.0) - 7.5) < 1e-12
+    # non-finite or zero curvature keeps the previous value
+    assert pcal.bb_eta("bb2", 3, s, 0 * s, 2.0, 1.0) == 2.0

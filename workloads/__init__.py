@@ -1,0 +1,301 @@
+"""Seeded synthetic workloads: meshes, nuclei and random starting blocks.
+
+This module produces *inputs only*.  It holds none of the method's arithmetic
+(no assembly, no quadrature, no iteration); both the CPU oracle and the HIP
+library consume what it returns.  Every random draw goes through
+``numpy.random.default_rng(seed)`` (PCG64), so a seed fully determines a
+workload.
+
+Meshes are tensor-product grids split into tetrahedra (Kuhn/Freudenthal split,
+six tetrahedra per hexahedral cell).  Graded grids follow the mesh-size law of
+Section 4.2 (eq. meshsizefunction), h = min_j(gamma1 Z_j^{-2/5} r_j^{6/5},
+gamma2), applied per axis with r_j the distance along that axis, which is a
+lower bound on the 3-D distance and therefore refines at least as much as the
+law asks.  Nodes on the boundary of the box carry the homogeneous Dirichlet
+condition of the H^1_0 space (Section 2.2).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Mesh",
+    "Workload",
+    "uniform_axis",
+    "graded_axis",
+    "kuhn_mesh",
+    "sample_cluster",
+    "random_block",
+    "make_workload",
+    "CONFIGS",
+]
+
+
+@dataclasses.dataclass
+class Mesh:
+    """Tetrahedral mesh.
+
+    xyz:       float64 [n_nodes, 3] node coordinates (bohr)
+    tets:      int32   [n_tets, 4]  node indices of each tetrahedron
+    dirichlet: uint8   [n_nodes]    1 on the boundary of the box, else 0
+    cells:     (nx, ny, nz) cells per axis of the underlying tensor grid
+    """
+
+    xyz: np.ndarray
+    tets: np.ndarray
+    dirichlet: np.ndarray
+    cells: tuple
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_tets(self) -> int:
+        return int(self.tets.shape[0])
+
+    @property
+    def n_dofs(self) -> int:
+        return int(self.n_nodes - int(self.dirichlet.sum()))
+
+
+@dataclasses.dataclass
+class Workload:
+    """A complete problem instance (inputs only)."""
+
+    name: str
+    mesh: Mesh
+    Z: np.ndarray          # float64 [M] nuclear charges
+    R: np.ndarray          # float64 [M, 3] nuclear positions
+    p: int                 # number of orbitals (columns of X)
+    beta: float            # penalty parameter of the augmented Lagrangian
+    scf: bool              # True: H depends on X (full Kohn-Sham); False: fixed H
+    seed: int
+    notes: str = ""
+
+
+# ----------------------------------------------------------------------------
+# 1-D grids
+# ----------------------------------------------------------------------------
+
+def uniform_axis(lo: float, hi: float, cells: int) -> np.ndarray:
+    return np.linspace(lo, hi, cells + 1)
+
+
+def _merge_anchors(anchors: Sequence[float], zs: Sequence[float], gap: float):
+    order = np.argsort(anchors)
+    out_a: List[float] = []
+    out_z: List[float] = []
+    for i in order:
+        a, z = float(anchors[i]), float(zs[i])
+        if out_a and a - out_a[-1] < gap:
+            out_z[-1] = max(out_z[-1], z)
+            continue
+        out_a.append(a)
+        out_z.append(z)
+    return np.array(out_a), np.array(out_z)
+
+
+def graded_axis(lo: float, hi: float, anchors: Sequence[float], zs: Sequence[float],
+                gamma1: float, gamma2: float, hmin: float, samples: int = 4096) -> np.ndarray:
+    """Node coordinates on [lo, hi] graded by the per-axis mesh-size law.
+
+    Every anchor (a nuclear coordinate on this axis) becomes a node.  Between
+    consecutive anchors the cell count is ceil(int dx / h(x)) and nodes are
+    placed at equal increments of int dx / h(x).
+    """
+    a, z = _merge_anchors(anchors, zs, 0.5 * hmin)
+    keep = (a > lo + hmin) & (a < hi - hmin)
+    a, z = a[keep], z[keep]
+    breaks = np.concatenate([[lo], a, [hi]])
+
+    def h_of(x: np.ndarray) -> np.ndarray:
+        h = np.full_like(x, gamma2)
+        for aj, zj in zip(a, z):
+            h = np.minimum(h, gamma1 * zj ** (-0.4) * np.abs(x - aj) ** 1.2)
+        return np.clip(h, hmin, gamma2)
+
+    nodes = [lo]
+    for s0, s1 in zip(breaks[:-1], breaks[1:]):
+        x = np.linspace(s0, s1, samples)
+        inv = 1.0 / h_of(x)
+        F = np.concatenate([[0.0], np.cumsum(0.5 * (inv[1:] + inv[:-1]) * np.diff(x))])
+        ncell = max(1, int(math.ceil(F[-1] - 1e-9)))
+        targets = np.linspace(0.0, F[-1], ncell + 1)[1:]
+        xs = np.interp(targets, F, x)
+        xs[-1] = s1
+        nodes.extend(xs.tolist())
+    return np.asarray(nodes, dtype=np.float64)
+
+
+# ----------------------------------------------------------------------------
+# Tensor grid -> Kuhn tetrahedra
+# ----------------------------------------------------------------------------
+
+# The six tetrahedra of the unit cube that share the diagonal (0,0,0)-(1,1,1):
+# one per ordering of the three axes, walking one axis at a time.
+_KUHN_PATHS = []
+for _perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+    _c = [0, 0, 0]
+    _path = [tuple(_c)]
+    for _ax in _perm:
+        _c[_ax] = 1
+        _path.append(tuple(_c))
+    _KUHN_PATHS.append(_path)
+
+
+def kuhn_mesh(xs: np.ndarray, ys: np.ndarray, zs: np.ndarray) -> Mesh:
+    """Tensor grid of nodes (x fastest) split into 6 tetrahedra per cell."""
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    X, Y, Zc = np.meshgrid(xs, ys, zs, indexing="ij")
+    # node id = i + (nx+1) * (j + (ny+1) * k)
+    xyz = np.stack([X.transpose(2, 1, 0).ravel(), Y.transpose(2, 1, 0).ravel(),
+                    Zc.transpose(2, 1, 0).ravel()], axis=1).astype(np.float64)
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci = ci.transpose(2, 1, 0).ravel()
+    cj = cj.transpose(2, 1, 0).ravel()
+    ck = ck.transpose(2, 1, 0).ravel()
+    n_cells = ci.size
+    tets = np.empty((n_cells, 6, 4), dtype=np.int64)
+    for t, path in enumerate(_KUHN_PATHS):
+        for v, (dx, dy, dz) in enumerate(path):
+            tets[:, t, v] = nid(ci + dx, cj + dy, ck + dz)
+    tets = tets.reshape(-1, 4).astype(np.int32)
+
+    ii = np.arange(nx + 1)
+    jj = np.arange(ny + 1)
+    kk = np.arange(nz + 1)
+    I, J, K = np.meshgrid(ii, jj, kk, indexing="ij")
+    I = I.transpose(2, 1, 0).ravel()
+    J = J.transpose(2, 1, 0).ravel()
+    K = K.transpose(2, 1, 0).ravel()
+    bnd = (I == 0) | (I == nx) | (J == 0) | (J == ny) | (K == 0) | (K == nz)
+    return Mesh(xyz=xyz, tets=tets, dirichlet=bnd.astype(np.uint8), cells=(nx, ny, nz))
+
+
+def graded_mesh(half: float, Z: np.ndarray, R: np.ndarray, gamma1: float, gamma2: float,
+                hmin: float) -> Mesh:
+    axes = [graded_axis(-half, half, R[:, d], Z, gamma1, gamma2, hmin) for d in range(3)]
+    return kuhn_mesh(*axes)
+
+
+def graded_mesh_for_dofs(half: float, Z: np.ndarray, R: np.ndarray, target_dofs: int,
+                         gamma2: float, hmin: float, iters: int = 40) -> tuple:
+    """Bisection on gamma1 so that the interior DOF count is close to target."""
+
+    def dofs(g1):
+        ax = [graded_axis(-half, half, R[:, d], Z, g1, gamma2, hmin) for d in range(3)]
+        return int(np.prod([len(a) - 2 for a in ax]))
+
+    lo, hi = 1e-3, 50.0          # dofs(lo) large, dofs(hi) small
+    for _ in range(iters):
+        mid = math.sqrt(lo * hi)
+        if dofs(mid) > target_dofs:
+            lo = mid
+        else:
+            hi = mid
+    g1 = lo if abs(dofs(lo) - target_dofs) <= abs(dofs(hi) - target_dofs) else hi
+    return graded_mesh(half, Z, R, g1, gamma2, hmin), g1
+
+
+# ----------------------------------------------------------------------------
+# Nuclei and random blocks
+# ----------------------------------------------------------------------------
+
+def sample_cluster(seed: int, M: int, zset: Sequence[int], half_box: float,
+                   min_sep: float, max_tries: int = 1_000_000):
+    """M nuclei with charges drawn uniformly from zset, positions uniform in
+    [-half_box, half_box]^3 by rejection so that every pair is >= min_sep apart."""
+    rng = np.random.default_rng(seed)
+    Z = rng.choice(np.asarray(zset, dtype=np.float64), size=M)
+    R = np.empty((M, 3))
+    k = 0
+    tries = 0
+    while k < M:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place nuclei with the requested separation")
+        c = rng.uniform(-half_box, half_box, size=3)
+        if k == 0 or np.min(np.linalg.norm(R[:k] - c, axis=1)) >= min_sep:
+            R[k] = c
+            k += 1
+    return Z, R
+
+
+def random_block(seed: int, n: int, p: int) -> np.ndarray:
+    """i.i.d. N(0,1) block, row-major n x p (a node's p values contiguous)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, p))
+
+
+# ----------------------------------------------------------------------------
+# The named workloads
+# ----------------------------------------------------------------------------
+
+def _c1(seed: int = 0, cells: int = 16) -> Workload:
+    ax = uniform_axis(-10.0, 10.0, cells)
+    mesh = kuhn_mesh(ax, ax, ax)
+    h = 20.0 / cells
+    Z = np.array([2.0])
+    R = np.array([[0.5 * h, 0.5 * h, 0.5 * h]])     # centre of the cell [0,h]^3
+    return Workload("c1", mesh, Z, R, p=4, beta=10.0, scf=False, seed=seed,
+                    notes=f"uniform {cells}^3 cells on [-10,10]^3, Z=2 at a cell centre")
+
+
+def _c2(seed: int = 0, target_dofs: int = 200_000) -> Workload:
+    Z, R = sample_cluster(seed, 4, (1, 6, 8), 3.0, 2.0)
+    mesh, g1 = graded_mesh_for_dofs(10.0, Z, R, target_dofs, gamma2=1.5, hmin=0.05)
+    p = int(math.ceil(Z.sum() / 2.0))
+    return Workload("c2", mesh, Z, R, p=p, beta=1.0, scf=True, seed=seed,
+                    notes=f"4 nuclei, graded, gamma1={g1:.4g}")
+
+
+def _cluster_box(M: int) -> float:
+    # keep the nuclear number density of 4 nuclei in [-3,3]^3
+    return 3.0 * (M / 4.0) ** (1.0 / 3.0)
+
+
+def _c3(seed: int = 0, target_dofs: int = 2_000_000, p: int = 128, M: int = 24) -> Workload:
+    a = _cluster_box(M)
+    Z, R = sample_cluster(seed, M, (1, 6, 7, 8), a, 2.0)
+    mesh, g1 = graded_mesh_for_dofs(a + 7.0, Z, R, target_dofs, gamma2=1.5, hmin=0.05)
+    return Workload("c3", mesh, Z, R, p=p, beta=1.0, scf=False, seed=seed,
+                    notes=f"{M} nuclei in [-{a:.3g},{a:.3g}]^3, graded, gamma1={g1:.4g}")
+
+
+def _c4(seed: int = 0, target_dofs: int = 8_000_000, p: int = 512) -> Workload:
+    w = _c3(seed, target_dofs=target_dofs, p=p, M=96)
+    w.name = "c4"
+    return w
+
+
+def make_workload(name: str, seed: int = 0, **kw) -> Workload:
+    name = name.lower()
+    if name == "c1":
+        return _c1(seed, **kw)
+    if name == "c2":
+        return _c2(seed, **kw)
+    if name in ("c3", "c5"):
+        w = _c3(seed, **kw)
+        w.name = name
+        return w
+    if name == "c4":
+        return _c4(seed, **kw)
+    raise ValueError(f"unknown workload {name!r}")
+
+
+CONFIGS = {
+    "c1": "uniform Kuhn grid 16^3 on [-10,10]^3, Z=2 at a cell centre, p=4, beta=10, fixed H",
+    "c2": "4 nuclei Z in {1,6,8} in [-3,3]^3 (sep>=2), graded grid n~2e5, p=ceil(sum Z/2), full SCF LDA",
+    "c3": "24 nuclei Z in {1,6,7,8}, graded grid n~2e6, p=128, fixed H (precision form)",
+    "c4": "96 nuclei, graded grid n~8e6, p=512, fixed H (precision form at scale)",
+    "c5": "c3-type held-out clusters (seeds 2000..2019), learned-preconditioner evaluation",
+}
