@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the PCAL hot path on one MI355X.
+
+Workload (default "c3"): a seeded 24-nucleus cluster (Z in {1,6,7,8}) on a
+graded P1 tetrahedral mesh with n ~ 2e6 interior DOFs and p = 128 orbitals,
+fixed Hamiltonian H = L/2 + M_ext.  One step = one PCAL iteration: dual SpMM,
+Gram, multiplier, gradient/kkt, the paper's preconditioner (Jacobi-PCG,
+m = 10 inner iterations), BB2 step and update, all in FP64.
+
+Printed (one JSON line): iterations per second over exactly --steps timed
+iterations after --warmup untimed ones, the roofline of the dominant kernel
+(the preconditioner's shifted SpMM) from HIP-event kernel timings, the time to
+residual 1e-6 for the plain FP64 method and for the mixed-precision form, and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "s to residual 1e-6 + iter/s: FP64 plain vs mixed-prec + learned precond"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--pcg-iters", type=int, default=10)
+    ap.add_argument("--no-converge", action="store_true", help="skip the time-to-residual runs")
+    ap.add_argument("--cpu-baseline", default="auto", choices=["auto", "skip"])
+    ap.add_argument("--max-iter", type=int, default=1000)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_spmm_shift(n, nnz, p, w):
+    """One launch of the preconditioner operator Q = (L/2 - lam B) D: read D
+    once, write Q once, read the CSR (values of L/2 and B, column index) and
+    the row pointers."""
+    return n * p * w * 2 + nnz * (2 * w + 4) + 8 * (n + 1)
+
+
+def algorithmic_bytes_spmm_dual(n, nnz, p, w):
+    return n * p * w * 3 + nnz * (2 * w + 4) + 8 * (n + 1)
+
+
+def traffic_from_profiles(kernel, workload):
+    """Measured HBM bytes per launch from committed rocprofv3 counter runs,
+    valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{kernel}@{workload}")
+    except Exception:
+        return None
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2007_14228_amd", "csrc", rec.get("source", "k_spmm.hip"))
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return rec.get("bytes_per_launch") if h == rec.get("source_sha") else None
+
+
+def run_to_tol(torch, solver_cls, w, X0, tol, params):
+    s = solver_cls()
+    s.load_workload(w)
+    s.set_params(tol=tol, **params)
+    s.set_x0(X0, orthonormalize=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, done, rc = s.step(params.get("max_iter", 1000) + 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    last = stats[-1]
+    out = dict(seconds=dt, iterations=len(stats) - 1, rel=last["rel"], energy=last["energy"],
+               converged=bool(last["rel"] < tol), iter_per_s=(len(stats) - 1) / dt if dt > 0 else None)
+    s.close()
+    return out
+
+
+def cpu_baseline(w, X0_host, pcg_iters):
+    """The oracle as it stands, one PCAL iteration (k = 0, with the paper's
+    preconditioner) on the full workload; reported as iterations per second."""
+    import threading
+    from oracle import fem, pcal
+    log("cpu baseline: oracle discretization")
+    t = time.perf_counter()
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    setup = time.perf_counter() - t
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, X0_host)
+    log(f"cpu baseline: setup {setup:.1f}s; timing one iteration")
+    t = time.perf_counter()
+    pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=1, precond="paper",
+                                    pcg_iters=pcg_iters))
+    dt = time.perf_counter() - t
+    # pcal(max_iter=1) evaluates X^0, steps once, then evaluates X^1 (no second step)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=1.0 / dt, unit="iter/s", cores=threads, kind="oracle",
+                sample=f"one full PCAL iteration (plus the evaluation of the next iterate) of the same "
+                       f"workload, FP64, paper preconditioner m={pcg_iters}: {dt:.2f} s; oracle setup "
+                       f"{setup:.1f} s not included")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "design only)"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(2)
+    import workloads as wl
+    from paper_2007_14228_amd import Solver
+
+    t = time.perf_counter()
+    w = wl.make_workload(a.workload, seed=a.seed)
+    n = w.mesh.n_dofs
+    p = w.p
+    log(f"workload {a.workload}: n={n} p={p} tets={w.mesh.n_tets} ({time.perf_counter() - t:.1f}s)")
+    X0_host = wl.random_block(1000 + a.seed, n, p)
+    X0 = torch.from_numpy(X0_host).to("cuda")
+
+    s = Solver()
+    t = time.perf_counter()
+    s.load_workload(w)
+    torch.cuda.synchronize()
+    log(f"device assembly {time.perf_counter() - t:.2f}s nnz={s.nnz}")
+    params = dict(beta=w.beta, precond="paper", pcg_iters=a.pcg_iters, max_iter=a.max_iter,
+                  scf=1 if w.scf else 0, energy_every=10 if p > 64 else 1)
+    s.set_params(tol=1e-30, **params)
+    s.set_x0(X0, orthonormalize=True)
+    s.step(a.warmup)
+    s.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, _, _ = s.step(a.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if len(stats) != a.steps:
+        raise RuntimeError("fewer steps than requested")
+    timers = {k: s.timer(k) for k in ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_axpy",
+                                      "bbdot", "density", "poisson", "assemble_h")}
+    s.timing(False)
+    log(f"{a.steps} steps in {dt:.3f}s; rel={stats[-1]['rel']:.3e}")
+    for k, (ms, cnt) in timers.items():
+        if cnt:
+            log(f"  {k:11s} {ms / cnt:8.3f} ms x {cnt}")
+
+    nnz = s.nnz
+    wbytes = 8
+    ms_shift, cnt_shift = timers["spmm_shift"]
+    if cnt_shift:
+        avg = ms_shift / cnt_shift
+        alg = algorithmic_bytes_spmm_shift(n, nnz, p, wbytes)
+        kern = "k_spmm_shift"
+    else:
+        ms_d, cnt_d = timers["spmm_dual"]
+        avg = ms_d / cnt_d
+        alg = algorithmic_bytes_spmm_dual(n, nnz, p, wbytes)
+        kern = "k_spmm_pair"
+    achieved = alg / (avg * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=kern, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kern, a.workload),
+                    avg_launch_ms=round(avg, 4), algorithmic_bytes_per_launch=int(alg))
+    s.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(a.steps / dt, 4),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(dt / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {wl.CONFIGS[a.workload]}", "n": n, "nnz": nnz, "p": p,
+                   "tets": w.mesh.n_tets, "seed": a.seed, "precond": f"paper (Jacobi-PCG m={a.pcg_iters})",
+                   "step_rule": "bb2", "beta": w.beta},
+        "roofline": roofline,
+        "kernel_ms": {k: round(v[0] / v[1], 4) for k, v in timers.items() if v[1]},
+    }
+
+    if not a.no_converge:
+        log("time to residual 1e-6: plain FP64")
+        plain = run_to_tol(torch, Solver, w, X0, 1e-6, params)
+        log(f"  {plain}")
+        log("time to residual 1e-6: mixed precision (FP32 blocks, FP64 p x p and refinement)")
+        mparams = dict(params, precision="f32", refine_tol=1e-5)
+        mixed = run_to_tol(torch, Solver, w, X0, 1e-6, mparams)
+        log(f"  {mixed}")
+        out["time_to_residual_1e-6"] = {"fp64_paper_precond": plain, "mixed_paper_precond": mixed}
+        if plain["converged"] and mixed["converged"]:
+            out["time_to_residual_1e-6"]["mixed_dE_vs_fp64_Ha"] = abs(mixed["energy"] - plain["energy"])
+
+    if a.cpu_baseline == "auto":
+        try:
+            out["cpu_baseline"] = cpu_baseline(w, X0_host, a.pcg_iters)
+        except Exception as e:  # the baseline must not hide the GPU result
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

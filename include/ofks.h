@@ -1,0 +1,205 @@
+/*
+ * ofks -- orthogonalization-free Kohn-Sham block solver for MI355X (gfx950).
+ *
+ * C ABI of the library libofks.so.  It implements the parallelizable
+ * column-wise augmented-Lagrangian iteration (PCAL, Section 3.3 of Gao, Hu,
+ * Kuang & Liu, "An orthogonalization-free parallelizable framework for
+ * all-electron calculations in density functional theory") on a P1
+ * tetrahedral finite-element discretization (Section 2.2).
+ *
+ * Conventions (apply to every entry point):
+ *  - Every call returns an int status: OFKS_OK (0), a positive warning, or a
+ *    negative error.  After a non-OK return ofks_last_error() gives a message.
+ *    No C++ exception crosses the ABI.
+ *  - All device work is enqueued on the HIP stream given to ofks_create.  Calls
+ *    that return host values synchronize that stream only.
+ *  - "host" pointers are read or written during the call only; "device"
+ *    pointers are caller-owned device memory that must stay valid during the
+ *    call.  The library owns the device memory it allocates for its state;
+ *    it allocates only in setup calls (mesh load, assemble, csr load, set_x0,
+ *    precision switch) and frees it in ofks_destroy.
+ *  - Blocks X (n x p) are row-major: the p values of one DOF are contiguous.
+ *    n counts interior (non-Dirichlet) nodes, numbered in node order.
+ *  - CSR matrices: row_ptr int64[n+1], col int32[nnz], columns sorted
+ *    ascending within a row, the diagonal present in every row.
+ *  - Call order: create -> (mesh_load, nuclei_set, assemble | csr_load)
+ *    -> set_params -> set_x0 -> step ...  Out-of-order calls return
+ *    OFKS_ESTATE.  A context is not thread-safe.
+ */
+#ifndef OFKS_H
+#define OFKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ofks_ctx ofks_ctx;
+
+enum {
+    OFKS_OK = 0,
+    OFKS_NOT_CONVERGED = 1,   /* warning: max_iter reached */
+    OFKS_EINVAL = -1,         /* bad argument */
+    OFKS_ESTATE = -2,         /* call out of order */
+    OFKS_EHIP = -3,           /* HIP runtime error */
+    OFKS_ECAPACITY = -4,      /* mesh exceeds a compiled-in bound */
+    OFKS_ENONFINITE = -5,     /* NaN/Inf in a p x p quantity */
+    OFKS_ENOTSPD = -6,        /* Gram matrix not positive definite */
+    OFKS_EZERONORM = -7       /* a column with zero B-norm */
+};
+
+/* Preconditioner choice (eq. precondition-T and the learned form). */
+enum { OFKS_PRECOND_NONE = 0, OFKS_PRECOND_PAPER = 1, OFKS_PRECOND_LEARNED = 2 };
+/* Step-size rule, Section 4.4 (Barzilai-Borwein variants). */
+enum { OFKS_STEP_BB2 = 0, OFKS_STEP_BB1 = 1, OFKS_STEP_ABB1 = 2, OFKS_STEP_ABB2 = 3,
+       OFKS_STEP_FIXED = 4 };
+/* Arithmetic of the n x p blocks.  p x p algebra is always FP64. */
+enum { OFKS_F64 = 0, OFKS_F32 = 1 };
+
+typedef struct {
+    double beta;            /* penalty parameter of L_beta (Section 4.4; default 1) */
+    double eta0;            /* > 0: first proximal parameter; 0: ||P0||_F/||X0||_F */
+    double tol;             /* stop when (kkt + fea)/kkt_0 < tol (Section 4.1) */
+    int32_t step_rule;      /* OFKS_STEP_* */
+    int32_t precond;        /* OFKS_PRECOND_* */
+    int32_t pcg_iters;      /* Jacobi-PCG iterations for T_i^{-1} G_i */
+    int32_t precision;      /* OFKS_F64 or OFKS_F32 */
+    int32_t precond_lambda; /* 0: diagonal of the eq. lambda2 multiplier, 1: of X^T H X */
+    int32_t max_iter;       /* iteration cap (paper: 1000) */
+    double occupation;      /* electrons per orbital f (2) */
+    int32_t scf;            /* 1: rebuild H(X) every iteration (Kohn-Sham); 0: fixed H */
+    int32_t energy_every;   /* evaluate the energy every k-th iteration (>= 1) */
+    double refine_tol;      /* F32 only: switch to FP64 when rel < refine_tol (0: never) */
+    double poisson_rtol;    /* Hartree CG relative residual */
+    int32_t poisson_max_iter;
+    int32_t fallback_window;/* learned form: W iterations of energy history */
+    int32_t fallback_hold;  /* learned form: iterations on the paper preconditioner after a fallback */
+    int32_t reserved[5];
+} ofks_params;
+
+typedef struct {
+    int32_t k;              /* iteration index of the iterate X^k these values describe */
+    int32_t precond_used;   /* OFKS_PRECOND_* applied in the step that produced X^{k+1} */
+    int32_t precision;      /* OFKS_F64 / OFKS_F32 of this iteration */
+    int32_t fell_back;      /* 1 if the learned form fell back in this iteration */
+    double energy;          /* SCF: E_KS; fixed H: tr(S^{-1} Lambda0) (NaN when skipped) */
+    double kkt;             /* ||H X - B X Lambda0||_F */
+    double fea;             /* ||X^T B X - I||_F */
+    double rel;             /* (kkt + fea) / kkt_0 */
+    double eta;             /* proximal parameter used for the step from X^k */
+    double ms;              /* wall time of this iteration (ms, stream-synchronous) */
+} ofks_iter_stats;
+
+/* Fills *p with the defaults documented above. */
+void ofks_default_params(ofks_params *p);
+
+/* Creates a context bound to a HIP stream (hipStream_t passed as void*; NULL =
+ * the null stream).  The current HIP device at this call is the context's device. */
+int ofks_create(ofks_ctx **out, void *hip_stream);
+int ofks_destroy(ofks_ctx *ctx);
+const char *ofks_last_error(const ofks_ctx *ctx);
+
+/* ---- discretization (Section 2.2) -------------------------------------- */
+
+/* Tetrahedral mesh: xyz host f64[n_nodes*3]; tets host i32[n_tets*4] node
+ * indices; dirichlet host u8[n_nodes] (1 = boundary node, value fixed to 0).
+ * Copies to the device.  EINVAL on out-of-range node indices. */
+int ofks_mesh_load(ofks_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_tets,
+                   const int32_t *tets, const uint8_t *dirichlet);
+
+/* Nuclei for V_ext(r) = -sum_j Z_j/|r - R_j| (eq. ext): Z host f64[M], R host f64[M*3]. */
+int ofks_nuclei_set(ofks_ctx *ctx, int32_t M, const double *Z, const double *R);
+
+/* On the device: interior-DOF numbering, sorted CSR pattern, stiffness L,
+ * mass B and M_ext by the 4-point degree-2 rule, and H = L/2 + M_ext
+ * (eq. hamiltonian without the density terms).  ECAPACITY if a node touches
+ * more than 128 tetrahedra or a row has more than 64 entries. */
+int ofks_assemble(ofks_ctx *ctx);
+
+/* Sizes of the assembled (or loaded) system. */
+int ofks_csr_info(ofks_ctx *ctx, int64_t *n, int64_t *nnz);
+
+/* Copies the pattern and values to host arrays (any pointer may be NULL):
+ * row_ptr[n+1], col[nnz], L[nnz], B[nnz], H[nnz] (current H). */
+int ofks_csr_get(ofks_ctx *ctx, int64_t *row_ptr, int32_t *col, double *L, double *B, double *H);
+
+/* Fixed problem given directly as CSR (all device pointers): H and B values;
+ * Lhalf (= L/2, for the preconditioner) may be NULL, then only
+ * OFKS_PRECOND_NONE is accepted.  Replaces any assembled system. */
+int ofks_csr_load(ofks_ctx *ctx, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                  const int32_t *col, const double *H, const double *B, const double *Lhalf);
+
+/* ---- problem setup ------------------------------------------------------ */
+
+int ofks_set_params(ofks_ctx *ctx, const ofks_params *params);
+
+/* Starting block X0 (device f64[n*p]).  b_orthonormalize = 1 applies the
+ * Cholesky-based Gram-Schmidt of Section 4.2 (X0 = V R^{-1}, R^T R = V^T B V);
+ * 0 takes X0 as given.  Allocates the iteration blocks for this p.  Resets
+ * the iteration counter.  ENOTSPD if V^T B V is not positive definite. */
+int ofks_set_x0(ofks_ctx *ctx, int32_t p, const double *dev_X0, int32_t b_orthonormalize);
+
+/* ---- main iteration (Algorithm PCAL) -------------------------------------- */
+
+/* Runs up to max_steps iterations.  stats (host, may be NULL) receives one
+ * entry per iteration evaluated; *n_stats their count; *done = 1 once the
+ * stopping rule holds or max_iter is reached.  Returns OFKS_OK, or
+ * OFKS_NOT_CONVERGED when max_iter was reached, or an error. */
+int ofks_step(ofks_ctx *ctx, int32_t max_steps, ofks_iter_stats *stats, int32_t *n_stats,
+              int32_t *done);
+
+/* kkt, fea and rel of the current iterate (evaluates them if needed). */
+int ofks_residual(ofks_ctx *ctx, double *kkt, double *fea, double *rel);
+
+/* Energy of the current iterate.  parts (host f64[8]): SCF: kinetic+external
+ * one-electron sum f tr(X^T (L/2 + M_ext) X), Hartree, xc, nuclear, total,
+ * electron count, f tr(Lambda0), int v_xc rho; fixed H: parts[4] = tr(S^{-1} Lambda0). */
+int ofks_energy(ofks_ctx *ctx, double *parts);
+
+/* Post-processing (Section 4.3): Rayleigh-Ritz on (Lambda0, S), X <- X Y.
+ * eigs host f64[p] ascending. */
+int ofks_postprocess(ofks_ctx *ctx, double *eigs);
+
+/* Current normalized iterate X^k into dev_X (device f64[n*p]). */
+int ofks_get_x(ofks_ctx *ctx, double *dev_X);
+
+/* SCF: density rho at the 4 quadrature points of every tetrahedron of the
+ * current iterate, dev_rho device f64[n_tets*4]. */
+int ofks_get_density(ofks_ctx *ctx, double *dev_rho);
+
+/* ---- single kernels, for parity checks ----------------------------------- */
+
+/* HX = H X and BX = B X (dual SpMM) on the current system; device f64 blocks n x p. */
+int ofks_spmm(ofks_ctx *ctx, int32_t p, const double *X, double *HX, double *BX);
+
+/* S = X^T BX and L0 = X^T HX (tall-skinny Gram), host f64[p*p] each, not symmetrized. */
+int ofks_gram(ofks_ctx *ctx, int32_t p, const double *X, const double *HX, const double *BX,
+              double *S, double *L0);
+
+/* P = T^{-1} G columnwise by the fixed-iteration Jacobi-PCG of the paper
+ * preconditioner; lam host f64[p]; columns with lam >= 0 are copied. */
+int ofks_precondition(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, double *P);
+
+/* SCF pieces for the iterate X (device f64 n x p, used as given):
+ * rho_q, eps_q, vxc_q device f64[n_tets*4] (any may be NULL), U device f64[n]
+ * (Hartree potential, may be NULL), parts host f64[4] = {int rho, int eps rho,
+ * int vxc rho, U.b/2} (may be NULL).  Also rebuilds H = H(X). */
+int ofks_build_hamiltonian(ofks_ctx *ctx, int32_t p, const double *X, double *rho_q,
+                           double *eps_q, double *vxc_q, double *U, double *parts);
+
+/* ---- timing ------------------------------------------------------------ */
+
+/* Kernel timers (HIP events on the context stream).  enable = 1 starts
+ * recording and clears the totals. */
+int ofks_timing(ofks_ctx *ctx, int32_t enable);
+/* Totals for a kernel class: name is one of "spmm_dual", "spmm_shift",
+ * "gram", "update_a", "update_b", "pcg_axpy", "density", "poisson", "assemble_h",
+ * "bbdot", "mlp".  ms = summed duration, launches = count. */
+int ofks_timer_get(ofks_ctx *ctx, const char *name, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OFKS_H */

@@ -1,0 +1,105 @@
+"""ctypes declarations of libofks.so (the C ABI in include/ofks.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libofks.so")
+
+OFKS_OK = 0
+OFKS_NOT_CONVERGED = 1
+PRECOND = {"none": 0, "paper": 1, "learned": 2}
+STEP = {"bb2": 0, "bb1": 1, "abb1": 2, "abb2": 3, "fixed": 4}
+PRECISION = {"f64": 0, "f32": 1}
+
+_c_double = ctypes.c_double
+_c_int32 = ctypes.c_int32
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("beta", _c_double),
+        ("eta0", _c_double),
+        ("tol", _c_double),
+        ("step_rule", _c_int32),
+        ("precond", _c_int32),
+        ("pcg_iters", _c_int32),
+        ("precision", _c_int32),
+        ("precond_lambda", _c_int32),
+        ("max_iter", _c_int32),
+        ("occupation", _c_double),
+        ("scf", _c_int32),
+        ("energy_every", _c_int32),
+        ("refine_tol", _c_double),
+        ("poisson_rtol", _c_double),
+        ("poisson_max_iter", _c_int32),
+        ("fallback_window", _c_int32),
+        ("fallback_hold", _c_int32),
+        ("reserved", _c_int32 * 5),
+    ]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [
+        ("k", _c_int32),
+        ("precond_used", _c_int32),
+        ("precision", _c_int32),
+        ("fell_back", _c_int32),
+        ("energy", _c_double),
+        ("kkt", _c_double),
+        ("fea", _c_double),
+        ("rel", _c_double),
+        ("eta", _c_double),
+        ("ms", _c_double),
+    ]
+
+
+# (name, restype, argtypes)
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+SIGNATURES = [
+    ("ofks_default_params", None, [ctypes.POINTER(Params)]),
+    ("ofks_create", I32, [ctypes.POINTER(P), P]),
+    ("ofks_destroy", I32, [P]),
+    ("ofks_last_error", ctypes.c_char_p, [P]),
+    ("ofks_mesh_load", I32, [P, I64, P, I64, P, P]),
+    ("ofks_nuclei_set", I32, [P, I32, P, P]),
+    ("ofks_assemble", I32, [P]),
+    ("ofks_csr_info", I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+    ("ofks_csr_get", I32, [P, P, P, P, P, P]),
+    ("ofks_csr_load", I32, [P, I64, I64, P, P, P, P, P]),
+    ("ofks_set_params", I32, [P, ctypes.POINTER(Params)]),
+    ("ofks_set_x0", I32, [P, I32, P, I32]),
+    ("ofks_step", I32, [P, I32, ctypes.POINTER(IterStats), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+    ("ofks_residual", I32, [P, ctypes.POINTER(_c_double), ctypes.POINTER(_c_double), ctypes.POINTER(_c_double)]),
+    ("ofks_energy", I32, [P, P]),
+    ("ofks_postprocess", I32, [P, P]),
+    ("ofks_get_x", I32, [P, P]),
+    ("ofks_get_density", I32, [P, P]),
+    ("ofks_spmm", I32, [P, I32, P, P, P]),
+    ("ofks_gram", I32, [P, I32, P, P, P, P, P]),
+    ("ofks_precondition", I32, [P, I32, P, P, P]),
+    ("ofks_build_hamiltonian", I32, [P, I32, P, P, P, P, P, P]),
+    ("ofks_timing", I32, [P, I32]),
+    ("ofks_timer_get", I32, [P, ctypes.c_char_p, ctypes.POINTER(_c_double), ctypes.POINTER(I64)]),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2007_14228_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

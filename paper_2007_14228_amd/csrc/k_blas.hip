@@ -1,0 +1,746 @@
+// Block (n x p) kernels of the PCAL iteration.
+//
+//  k_gram        X^T [BX | HX] as split-K partial tiles (Algorithm PCAL,
+//                eq. lambda2 needs S = X^T B X and Lambda0 = X^T H X).
+//  k_colsum      fixed-order reduction of per-block partials.
+//  k_rowgemm     [G | R] = (BX D^-1) [C | C'] + (HX D^-1) with the update
+//                epilogues (gradient of L_beta, residual norm for kkt, the
+//                start of the preconditioner's CG), or a plain Y = X M.
+//  k_pcg_xr      x += alpha d, r -= alpha q, <r, J r>   (inner CG step)
+//  k_pcg_dir     d = J r + beta d
+//  k_pcg_scalars alpha / beta per column on the device
+//  k_bbdot       <S,Y>, <Y,Y>, <S,S>, ||P||^2, ||X||^2 for the BB step
+//  k_update_b    X~ = X - P / eta with X = X~ D^-1; keeps X as X^{k-1}
+//  k_coldot      per-column sums of A .* B (column B-norms)
+//
+// Every reduction writes per-block partials that a fixed-order pass sums, so
+// results do not depend on scheduling.
+#include "common.hpp"
+
+namespace ofks {
+
+// ---------------------------------------------------------------------------
+// Gram: part[split][a][c] = sum_{rows of split} X[r][a] * Y[r][c],
+// Y = [BX | HX] (c < p -> BX[:, c], else HX[:, c - p]).
+// Tile (16*MT) x (16*NT), 256 threads as 16 x 16, thread (ty, tx) owns rows
+// a = a0 + ty + 16 i and columns c = c0 + tx + 16 j.
+// ---------------------------------------------------------------------------
+template <typename T, typename ACC, int MT, int NT>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, int p, int64_t rows_per_split,
+                                             const T *__restrict__ X, const T *__restrict__ BX,
+                                             const T *__restrict__ HX, double *__restrict__ part) {
+    constexpr int TM = 16 * MT, TN = 16 * NT, KC = 16;
+    __shared__ T As[KC][TM];
+    __shared__ T Bs[KC][TN];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int a0 = blockIdx.x * TM, c0 = blockIdx.y * TN;
+    const int64_t r_begin = (int64_t)blockIdx.z * rows_per_split;
+    const int64_t r_end = min(n, r_begin + rows_per_split);
+    const int p2 = 2 * p;
+    ACC acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = ACC(0);
+
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
+        for (int idx = threadIdx.x; idx < KC * TM; idx += 256) {
+            const int kr = idx / TM, cc = idx % TM;
+            const int64_t r = r0 + kr;
+            const int a = a0 + cc;
+            As[kr][cc] = (r < r_end && a < p) ? X[r * p + a] : T(0);
+        }
+        for (int idx = threadIdx.x; idx < KC * TN; idx += 256) {
+            const int kr = idx / TN, cc = idx % TN;
+            const int64_t r = r0 + kr;
+            const int c = c0 + cc;
+            T v = T(0);
+            if (r < r_end && c < p2) v = (c < p) ? BX[r * p + c] : HX[r * p + (c - p)];
+            Bs[kr][cc] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            ACC av[MT], bv[NT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) av[i] = (ACC)As[k][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) bv[j] = (ACC)Bs[k][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    double *out = part + (int64_t)blockIdx.z * p * p2;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        const int a = a0 + ty + 16 * i;
+        if (a >= p) continue;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int c = c0 + tx + 16 * j;
+            if (c < p2) out[(int64_t)a * p2 + c] = (double)acc[i][j];
+        }
+    }
+}
+
+// out[m] = sum_{b < nb} part[b * m_total + m] for m in [0, m_total); one block
+// per output, fixed strided partition then a fixed tree.
+__global__ __launch_bounds__(256) void k_colsum(int64_t nb, int64_t m_total,
+                                               const double *__restrict__ part,
+                                               double *__restrict__ out) {
+    __shared__ double red[256];
+    const int64_t m = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) s += part[b * m_total + m];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[m] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Row GEMM with epilogues.  out[r][c] = sum_k A[r][k] sa[k] M[k][c] (+ addend)
+// for c in [0, N).  Tile: 16*MT rows x 16*NT columns; thread (ty, tx) owns
+// rows r0 + ty + 16 i, columns c0 + tx + 16 j.  Persistent over row tiles.
+// ---------------------------------------------------------------------------
+enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2 };
+
+struct GradArgs {
+    const void *HX;       // n x p, unnormalized (scaled by dinv here)
+    void *P;              // out: gradient (no CG) / identity-branch columns
+    void *R;              // out: CG residual r = G (active columns)
+    void *D;              // out: CG direction d = J G (active columns)
+    const double *lhd;    // diag(L/2), n
+    const double *bd;     // diag(B), n
+    const void *lam;      // shift lambda_c of T_c, p
+    const uint8_t *active;// column uses the CG preconditioner
+    double *part;         // per block: [0] ||R||^2, [1 + c] <r_c, J r_c>
+};
+
+template <typename T, int MT, int NT, int EPI>
+__global__ __launch_bounds__(256) void k_rowgemm(int64_t n, int p, int N, const T *__restrict__ A,
+                                                const T *__restrict__ sa,
+                                                const T *__restrict__ M, T *__restrict__ Y,
+                                                GradArgs ga) {
+    constexpr int TR = 16 * MT, TC = 16 * NT, KC = 16;
+    __shared__ T As[TR][KC + 1];
+    __shared__ T Ms[KC][TC];
+    __shared__ double red[256];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int c0 = blockIdx.y * TC;
+    const int64_t ntiles = (n + TR - 1) / TR;
+    double r2 = 0.0;
+    double rz[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) rz[j] = 0.0;
+    const T *HX = (const T *)ga.HX;
+    const T *lamv = (const T *)ga.lam;
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * TR;
+        T acc[MT][NT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[i][j] = T(0);
+        for (int k0 = 0; k0 < p; k0 += KC) {
+            for (int idx = threadIdx.x; idx < TR * KC; idx += 256) {
+                const int rr = idx / KC, kk = idx % KC;
+                const int64_t r = r0 + rr;
+                const int k = k0 + kk;
+                As[rr][kk] = (r < n && k < p) ? A[r * p + k] * sa[k] : T(0);
+            }
+            for (int idx = threadIdx.x; idx < KC * TC; idx += 256) {
+                const int kk = idx / TC, cc = idx % TC;
+                const int k = k0 + kk, c = c0 + cc;
+                Ms[kk][cc] = (k < p && c < N) ? M[(int64_t)k * N + c] : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                T av[MT], mv[NT];
+#pragma unroll
+                for (int i = 0; i < MT; ++i) av[i] = As[ty + 16 * i][kk];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) mv[j] = Ms[kk][tx + 16 * j];
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) acc[i][j] = fma(av[i], mv[j], acc[i][j]);
+            }
+            __syncthreads();
+        }
+        // epilogue
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            const int64_t r = r0 + ty + 16 * i;
+            if (r >= n) continue;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int c = c0 + tx + 16 * j;
+                if (c >= N) continue;
+                if (EPI == EPI_PLAIN) {
+                    Y[r * N + c] = acc[i][j];
+                } else {
+                    const int cc = c < p ? c : c - p;
+                    const T v = fma(HX[r * p + cc], sa[cc], acc[i][j]);
+                    if (c >= p) {
+                        r2 += (double)v * (double)v;
+                    } else if (EPI == EPI_GRAD) {
+                        ((T *)ga.P)[r * p + c] = v;
+                    } else {  // EPI_GRAD_PCG
+                        if (ga.active[c]) {
+                            const T jinv = T(1) / (T(ga.lhd[r]) - lamv[c] * T(ga.bd[r]));
+                            const T z = v * jinv;
+                            ((T *)ga.R)[r * p + c] = v;
+                            ((T *)ga.D)[r * p + c] = z;
+                            rz[j] += (double)v * (double)z;
+                        } else {
+                            ((T *)ga.P)[r * p + c] = v;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (EPI == EPI_PLAIN) return;
+    // block partials: red over all threads for r2; per column for rz
+    double *part = ga.part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (1 + p);
+    red[threadIdx.x] = r2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[0] = red[0];
+    __syncthreads();
+    if (EPI == EPI_GRAD_PCG) {
+        for (int c = threadIdx.x; c < p; c += 256)
+            if (c < c0 || c >= c0 + TC) part[1 + c] = 0.0;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            red[threadIdx.x] = rz[j];
+            __syncthreads();
+            if (ty == 0) {
+                double s = 0.0;
+                for (int k = 0; k < 16; ++k) s += red[k * 16 + tx];
+                const int c = c0 + tx + 16 * j;
+                if (c < p) part[1 + c] = s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lane-per-column-slice kernels over n x p blocks (same mapping as SpMM).
+// ---------------------------------------------------------------------------
+
+// x = (first ? 0 : x) + alpha d ; r -= alpha q ; partial <r, J r>.  Persistent.
+template <typename T, int V, int CH>
+__global__ __launch_bounds__(256) void k_pcg_xr(int64_t n, int p, int lpr_log2, int first,
+                                               const T *__restrict__ alpha,
+                                               const uint8_t *__restrict__ active,
+                                               const double *__restrict__ lhd,
+                                               const double *__restrict__ bd,
+                                               const T *__restrict__ lam, const T *__restrict__ D,
+                                               const T *__restrict__ Q, T *__restrict__ Xo,
+                                               T *__restrict__ R, double *__restrict__ part) {
+    extern __shared__ double red[];
+    const int lpr = 1 << lpr_log2;
+    const int groups = blockDim.x >> lpr_log2;
+    const int g = threadIdx.x >> lpr_log2;
+    const int lane = threadIdx.x & (lpr - 1);
+    double dot[CH][V];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int v = 0; v < V; ++v) dot[ch][v] = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * groups + g; row < n; row += (int64_t)gridDim.x * groups) {
+        const T ld = (T)lhd[row], bdv = (T)bd[row];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const int c0 = (lane + ch * lpr) * V;
+            if (c0 >= p) continue;
+            T d[V], q[V], x[V], r[V];
+            load_vec<T, V>(D + row * p + c0, d);
+            load_vec<T, V>(Q + row * p + c0, q);
+            load_vec<T, V>(R + row * p + c0, r);
+            if (first) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) x[v] = T(0);
+            } else {
+                load_vec<T, V>(Xo + row * p + c0, x);
+            }
+            bool any = false;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (!active[c0 + v]) continue;
+                any = true;
+                const T a = alpha[c0 + v];
+                x[v] = fma(a, d[v], x[v]);
+                r[v] = fma(-a, q[v], r[v]);
+                const T z = r[v] / (ld - lam[c0 + v] * bdv);
+                dot[ch][v] += (double)r[v] * (double)z;
+            }
+            if (any) {
+                // inactive columns of a vector keep their stored values
+                T xo[V], ro[V];
+                if (!first) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) xo[v] = x[v];
+                } else {
+                    load_vec<T, V>(Xo + row * p + c0, xo);
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        if (active[c0 + v]) xo[v] = x[v];
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) ro[v] = r[v];
+                store_vec<T, V>(Xo + row * p + c0, xo);
+                store_vec<T, V>(R + row * p + c0, ro);
+            }
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = (lane + ch * lpr) * V;
+        if (c0 < p) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) red[g * p + c0 + v] = dot[ch][v];
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < p; c += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < groups; ++k) s += red[k * p + c];
+        part[(int64_t)blockIdx.x * p + c] = s;
+    }
+}
+
+// d = J r + beta d on active columns.
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_pcg_dir(int64_t n, int p, int lpr_log2,
+                                                const T *__restrict__ beta,
+                                                const uint8_t *__restrict__ active,
+                                                const double *__restrict__ lhd,
+                                                const double *__restrict__ bd,
+                                                const T *__restrict__ lam, const T *__restrict__ R,
+                                                T *__restrict__ D) {
+    const int lpr = 1 << lpr_log2;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lpr_log2;
+    const int lane = threadIdx.x & (lpr - 1);
+    if (row >= n) return;
+    const T ld = (T)lhd[row], bdv = (T)bd[row];
+    for (int c0 = lane * V; c0 < p; c0 += lpr * V) {
+        T r[V], d[V];
+        load_vec<T, V>(R + row * p + c0, r);
+        load_vec<T, V>(D + row * p + c0, d);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (active[c0 + v]) d[v] = fma(beta[c0 + v], d[v], r[v] / (ld - lam[c0 + v] * bdv));
+        store_vec<T, V>(D + row * p + c0, d);
+    }
+}
+
+// alpha_c = rz_c / dq_c (0 when dq_c <= 0);  beta_c = rz_new_c / rz_c (0 when rz_c <= 0).
+template <typename T>
+__global__ void k_pcg_alpha(int p, const double *__restrict__ dq, const double *__restrict__ rz,
+                            T *__restrict__ alpha) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < p) alpha[c] = dq[c] > 0.0 ? (T)(rz[c] / dq[c]) : T(0);
+}
+
+template <typename T>
+__global__ void k_pcg_beta(int p, const double *__restrict__ rz_new, double *__restrict__ rz,
+                           T *__restrict__ beta) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < p) {
+        beta[c] = rz[c] > 0.0 ? (T)(rz_new[c] / rz[c]) : T(0);
+        rz[c] = rz_new[c];
+    }
+}
+
+// BB sums.  x = Xt .* dinv; s = x - Xp; y = P - Pp.
+// part[block][5] = {<s,y>, <y,y>, <s,s>, <P,P>, <x,x>}; Xp/Pp may be null.
+template <typename T, int V, int CH>
+__global__ __launch_bounds__(256) void k_bbdot(int64_t n, int p, int lpr_log2,
+                                              const T *__restrict__ Xt, const T *__restrict__ dinv,
+                                              const T *__restrict__ P, const T *__restrict__ Xp,
+                                              const T *__restrict__ Pp, double *__restrict__ part) {
+    __shared__ double red[5][256];
+    const int lpr = 1 << lpr_log2;
+    const int groups = blockDim.x >> lpr_log2;
+    const int g = threadIdx.x >> lpr_log2;
+    const int lane = threadIdx.x & (lpr - 1);
+    double s5[5] = {0, 0, 0, 0, 0};
+    const bool hist = Xp != nullptr;
+    for (int64_t row = (int64_t)blockIdx.x * groups + g; row < n; row += (int64_t)gridDim.x * groups) {
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const int c0 = (lane + ch * lpr) * V;
+            if (c0 >= p) continue;
+            T xt[V], pv[V];
+            load_vec<T, V>(Xt + row * p + c0, xt);
+            load_vec<T, V>(P + row * p + c0, pv);
+            T xp[V], pp[V];
+            if (hist) {
+                load_vec<T, V>(Xp + row * p + c0, xp);
+                load_vec<T, V>(Pp + row * p + c0, pp);
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double x = (double)(xt[v] * dinv[c0 + v]);
+                const double pd = (double)pv[v];
+                s5[3] += pd * pd;
+                s5[4] += x * x;
+                if (hist) {
+                    const double s = x - (double)xp[v];
+                    const double y = pd - (double)pp[v];
+                    s5[0] += s * y;
+                    s5[1] += y * y;
+                    s5[2] += s * s;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = s5[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) part[(int64_t)blockIdx.x * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Xp = Xt .* dinv ; Xt = Xp - P / eta
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_update_b(int64_t n, int p, int lpr_log2,
+                                                 const T *__restrict__ dinv, T eta,
+                                                 const T *__restrict__ P, T *__restrict__ Xt,
+                                                 T *__restrict__ Xp) {
+    const int lpr = 1 << lpr_log2;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lpr_log2;
+    const int lane = threadIdx.x & (lpr - 1);
+    if (row >= n) return;
+    for (int c0 = lane * V; c0 < p; c0 += lpr * V) {
+        T xt[V], pv[V], x[V], xn[V];
+        load_vec<T, V>(Xt + row * p + c0, xt);
+        load_vec<T, V>(P + row * p + c0, pv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            x[v] = xt[v] * dinv[c0 + v];
+            xn[v] = x[v] - pv[v] / eta;
+        }
+        if (Xp) store_vec<T, V>(Xp + row * p + c0, x);
+        store_vec<T, V>(Xt + row * p + c0, xn);
+    }
+}
+
+// per-column sums of A .* B (and of A .* A when AA is set), persistent;
+// part[block][p] (or [block][2p]).
+template <typename T, int V, int CH>
+__global__ __launch_bounds__(256) void k_coldot(int64_t n, int p, int lpr_log2,
+                                               const T *__restrict__ A, const T *__restrict__ B,
+                                               double *__restrict__ part) {
+    extern __shared__ double red[];
+    const int lpr = 1 << lpr_log2;
+    const int groups = blockDim.x >> lpr_log2;
+    const int g = threadIdx.x >> lpr_log2;
+    const int lane = threadIdx.x & (lpr - 1);
+    double dot[CH][V];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int v = 0; v < V; ++v) dot[ch][v] = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * groups + g; row < n; row += (int64_t)gridDim.x * groups) {
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const int c0 = (lane + ch * lpr) * V;
+            if (c0 >= p) continue;
+            T a[V], b[V];
+            load_vec<T, V>(A + row * p + c0, a);
+            load_vec<T, V>(B + row * p + c0, b);
+#pragma unroll
+            for (int v = 0; v < V; ++v) dot[ch][v] += (double)a[v] * (double)b[v];
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = (lane + ch * lpr) * V;
+        if (c0 < p) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) red[g * p + c0 + v] = dot[ch][v];
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < p; c += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < groups; ++k) s += red[k * p + c];
+        part[(int64_t)blockIdx.x * p + c] = s;
+    }
+}
+
+// Y = X .* s (column scale), optionally converting the element type
+template <typename S, typename D>
+__global__ void k_scale_copy(int64_t n, int p, const S *__restrict__ X, const S *__restrict__ sc,
+                             D *__restrict__ Y) {
+    const int64_t m = n * p;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        Y[i] = (D)(X[i] * sc[i % p]);
+}
+
+// Start of the columnwise CG of the preconditioner from x = 0:
+// r = G, d = J G on active columns, P = G on the others; part[block][p] = <r, J r>.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_init(int64_t n, int p, const uint8_t *__restrict__ active,
+                                                 const double *__restrict__ lhd,
+                                                 const double *__restrict__ bd, const T *__restrict__ lam,
+                                                 const T *__restrict__ G, T *__restrict__ R,
+                                                 T *__restrict__ D, T *__restrict__ P,
+                                                 double *__restrict__ part) {
+    extern __shared__ double red[];   // [256]
+    for (int c = 0; c < p; ++c) {
+        double s = 0.0;
+        for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+             r += (int64_t)gridDim.x * blockDim.x) {
+            const T g = G[r * p + c];
+            if (active[c]) {
+                const T z = g / (T(lhd[r]) - lam[c] * T(bd[r]));
+                R[r * p + c] = g;
+                D[r * p + c] = z;
+                s += (double)g * (double)z;
+            } else {
+                P[r * p + c] = g;
+            }
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * p + c] = red[0];
+        __syncthreads();
+    }
+}
+
+// f32 <-> f64 block conversion
+template <typename S, typename D>
+__global__ void k_convert(int64_t m, const S *__restrict__ a, D *__restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (D)a[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int ilog2c(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+template <typename T> static inline int vwidth(int p) {
+    if (sizeof(T) == 8) return (p % 2 == 0) ? 2 : 1;
+    return (p % 4 == 0) ? 4 : ((p % 2 == 0) ? 2 : 1);
+}
+static inline int lpr_l2(int p, int v) {
+    int l = ilog2c((p + v - 1) / v);
+    return l > 6 ? 6 : l;
+}
+
+template <typename T>
+hipError_t launch_gram(hipStream_t s, int64_t n, int p, int target_blocks, const T *X, const T *BX,
+                       const T *HX, double *part, int *nsplit_out) {
+    int mt, nt;
+    if (p <= 16) { mt = 1; nt = 2; }
+    else if (p <= 32) { mt = 2; nt = 4; }
+    else { mt = 4; nt = 4; }
+    const int tm = 16 * mt, tn = 16 * nt;
+    const int gx = (p + tm - 1) / tm, gy = (2 * p + tn - 1) / tn;
+    int64_t splits = target_blocks / (gx * gy);
+    if (splits < 1) splits = 1;
+    int64_t rps = (n + splits - 1) / splits;
+    rps = ((rps + 15) / 16) * 16;
+    if (rps < 16) rps = 16;
+    splits = (n + rps - 1) / rps;
+    if (splits < 1) splits = 1;
+    *nsplit_out = (int)splits;
+    dim3 grid(gx, gy, (unsigned)splits);
+    using ACC = T;
+    if (mt == 1) hipLaunchKernelGGL((k_gram<T, ACC, 1, 2>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    else if (mt == 2) hipLaunchKernelGGL((k_gram<T, ACC, 2, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    else hipLaunchKernelGGL((k_gram<T, ACC, 4, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(hipStream_t s, int64_t nb, int64_t m, const double *part, double *out) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)m), dim3(256), 0, s, nb, m, part, out);
+    return hipGetLastError();
+}
+
+// number of blocks along rows for k_rowgemm epilogues (fixed => deterministic)
+template <typename T>
+hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int grid_rows, const T *A,
+                          const T *sa, const T *M, T *Y, GradArgs ga, int *gx_out) {
+    const int mt = 4;
+    const int nt = (N <= 16) ? 1 : ((N <= 32) ? 2 : 4);
+    const int tr = 16 * mt, tc = 16 * nt;
+    const int64_t ntiles = (n + tr - 1) / tr;
+    int gx = grid_rows;
+    if (gx > ntiles) gx = (int)ntiles;
+    if (gx < 1) gx = 1;
+    const int gy = (N + tc - 1) / tc;
+    if (gx_out) *gx_out = gx;
+    dim3 grid(gx, gy);
+#define OFKS_RG(NT_)                                                                          \
+    if (nt == NT_) {                                                                          \
+        if (epi == EPI_PLAIN) hipLaunchKernelGGL((k_rowgemm<T, 4, NT_, EPI_PLAIN>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_rowgemm<T, 4, NT_, EPI_GRAD>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else hipLaunchKernelGGL((k_rowgemm<T, 4, NT_, EPI_GRAD_PCG>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        return hipGetLastError();                                                             \
+    }
+    OFKS_RG(1)
+    OFKS_RG(2)
+    OFKS_RG(4)
+#undef OFKS_RG
+    return hipErrorInvalidValue;
+}
+
+#define OFKS_CH_DISPATCH(KERNEL, ...)                                                         \
+    do {                                                                                      \
+        const int v = vwidth<T>(p);                                                           \
+        const int l2 = lpr_l2(p, v);                                                          \
+        const int chunks = (p + (v << l2) - 1) / (v << l2);                                   \
+        const size_t shm = (size_t)(256 >> l2) * p * sizeof(double);                          \
+        (void)shm;                                                                            \
+        if (v == 1 && chunks <= 1) { hipLaunchKernelGGL((KERNEL<T, 1, 1>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+        if (v == 1 && chunks <= 8) { hipLaunchKernelGGL((KERNEL<T, 1, 8>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+        if (v == 2 && chunks <= 1) { hipLaunchKernelGGL((KERNEL<T, 2, 1>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+        if (v == 2 && chunks <= 2) { hipLaunchKernelGGL((KERNEL<T, 2, 2>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+        if (v == 2 && chunks <= 4) { hipLaunchKernelGGL((KERNEL<T, 2, 4>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+        if (v == 2 && chunks <= 8) { hipLaunchKernelGGL((KERNEL<T, 2, 8>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+        if constexpr (sizeof(T) == 4) {                                                       \
+            if (v == 4 && chunks <= 1) { hipLaunchKernelGGL((KERNEL<T, 4, 1>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+            if (v == 4 && chunks <= 2) { hipLaunchKernelGGL((KERNEL<T, 4, 2>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+            if (v == 4 && chunks <= 4) { hipLaunchKernelGGL((KERNEL<T, 4, 4>), dim3(grid), dim3(256), SHM, s, n, p, l2, __VA_ARGS__); break; } \
+        }                                                                                     \
+        return hipErrorInvalidValue;                                                          \
+    } while (0)
+
+template <typename T>
+hipError_t launch_pcg_xr(hipStream_t s, int grid, int64_t n, int p, int first, const T *alpha,
+                         const uint8_t *active, const double *lhd, const double *bd, const T *lam,
+                         const T *D, const T *Q, T *X, T *R, double *part) {
+#define SHM shm
+    OFKS_CH_DISPATCH(k_pcg_xr, first, alpha, active, lhd, bd, lam, D, Q, X, R, part);
+#undef SHM
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coldot(hipStream_t s, int grid, int64_t n, int p, const T *A, const T *B,
+                         double *part) {
+#define SHM shm
+    OFKS_CH_DISPATCH(k_coldot, A, B, part);
+#undef SHM
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bbdot(hipStream_t s, int grid, int64_t n, int p, const T *Xt, const T *dinv,
+                        const T *P, const T *Xp, const T *Pp, double *part) {
+#define SHM 0
+    OFKS_CH_DISPATCH(k_bbdot, Xt, dinv, P, Xp, Pp, part);
+#undef SHM
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_dir(hipStream_t s, int64_t n, int p, const T *beta, const uint8_t *active,
+                          const double *lhd, const double *bd, const T *lam, const T *R, T *D) {
+    const int v = vwidth<T>(p);
+    const int l2 = lpr_l2(p, v);
+    const unsigned grid = (unsigned)(((n << l2) + 255) / 256);
+    if (v == 1) hipLaunchKernelGGL((k_pcg_dir<T, 1>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D);
+    else if (v == 2) hipLaunchKernelGGL((k_pcg_dir<T, 2>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D);
+    else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_pcg_dir<T, 4>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_update_b(hipStream_t s, int64_t n, int p, const T *dinv, T eta, const T *P, T *Xt,
+                           T *Xp) {
+    const int v = vwidth<T>(p);
+    const int l2 = lpr_l2(p, v);
+    const unsigned grid = (unsigned)(((n << l2) + 255) / 256);
+    if (v == 1) hipLaunchKernelGGL((k_update_b<T, 1>), dim3(grid), dim3(256), 0, s, n, p, l2, dinv, eta, P, Xt, Xp);
+    else if (v == 2) hipLaunchKernelGGL((k_update_b<T, 2>), dim3(grid), dim3(256), 0, s, n, p, l2, dinv, eta, P, Xt, Xp);
+    else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_update_b<T, 4>), dim3(grid), dim3(256), 0, s, n, p, l2, dinv, eta, P, Xt, Xp);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_scalars(hipStream_t s, int p, int which, const double *a, double *b, T *out) {
+    const unsigned grid = (unsigned)((p + 255) / 256);
+    if (which == 0) hipLaunchKernelGGL((k_pcg_alpha<T>), dim3(grid), dim3(256), 0, s, p, a, b, out);
+    else hipLaunchKernelGGL((k_pcg_beta<T>), dim3(grid), dim3(256), 0, s, p, a, b, out);
+    return hipGetLastError();
+}
+
+template <typename S, typename D>
+hipError_t launch_convert(hipStream_t s, int64_t m, const S *a, D *b) {
+    hipLaunchKernelGGL((k_convert<S, D>), dim3(2048), dim3(256), 0, s, m, a, b);
+    return hipGetLastError();
+}
+
+template <typename S, typename D>
+hipError_t launch_scale_copy(hipStream_t s, int64_t n, int p, const S *X, const S *sc, D *Y) {
+    hipLaunchKernelGGL((k_scale_copy<S, D>), dim3(2048), dim3(256), 0, s, n, p, X, sc, Y);
+    return hipGetLastError();
+}
+template hipError_t launch_scale_copy<double, double>(hipStream_t, int64_t, int, const double *, const double *, double *);
+template hipError_t launch_scale_copy<float, double>(hipStream_t, int64_t, int, const float *, const float *, double *);
+template hipError_t launch_scale_copy<float, float>(hipStream_t, int64_t, int, const float *, const float *, float *);
+
+template <typename T>
+hipError_t launch_pcg_init(hipStream_t s, int grid, int64_t n, int p, const uint8_t *active, const double *lhd,
+                           const double *bd, const T *lam, const T *G, T *R, T *D, T *P, double *part) {
+    hipLaunchKernelGGL((k_pcg_init<T>), dim3(grid), dim3(256), 256 * sizeof(double), s, n, p, active, lhd, bd,
+                       lam, G, R, D, P, part);
+    return hipGetLastError();
+}
+template hipError_t launch_pcg_init<double>(hipStream_t, int, int64_t, int, const uint8_t *, const double *,
+                                            const double *, const double *, const double *, double *, double *,
+                                            double *, double *);
+template hipError_t launch_pcg_init<float>(hipStream_t, int, int64_t, int, const uint8_t *, const double *,
+                                           const double *, const float *, const float *, float *, float *,
+                                           float *, double *);
+
+#define OFKS_INST(T)                                                                                  \
+    template hipError_t launch_gram<T>(hipStream_t, int64_t, int, int, const T *, const T *, const T *, double *, int *); \
+    template hipError_t launch_rowgemm<T>(hipStream_t, int, int64_t, int, int, int, const T *, const T *, const T *, T *, GradArgs, int *); \
+    template hipError_t launch_pcg_xr<T>(hipStream_t, int, int64_t, int, int, const T *, const uint8_t *, const double *, const double *, const T *, const T *, const T *, T *, T *, double *); \
+    template hipError_t launch_coldot<T>(hipStream_t, int, int64_t, int, const T *, const T *, double *); \
+    template hipError_t launch_bbdot<T>(hipStream_t, int, int64_t, int, const T *, const T *, const T *, const T *, const T *, double *); \
+    template hipError_t launch_pcg_dir<T>(hipStream_t, int64_t, int, const T *, const uint8_t *, const double *, const double *, const T *, const T *, T *); \
+    template hipError_t launch_update_b<T>(hipStream_t, int64_t, int, const T *, T, const T *, T *, T *); \
+    template hipError_t launch_pcg_scalars<T>(hipStream_t, int, int, const double *, double *, T *);
+OFKS_INST(double)
+OFKS_INST(float)
+template hipError_t launch_convert<double, float>(hipStream_t, int64_t, const double *, float *);
+template hipError_t launch_convert<float, double>(hipStream_t, int64_t, const float *, double *);
+
+}  // namespace ofks

@@ -1,0 +1,1430 @@
+// Host driver and C ABI of the ofks library.
+//
+// One PCAL iteration (Algorithm PCAL, Section 3.3) from the stored block
+// X~ (the previous step before its column B-normalization):
+//   [SCF]  B X~, column norms d, rho, v_xc, Hartree, H(X) re-assembly
+//   HX~, BX~                         dual SpMM
+//   S~ = X~^T B X~, L~ = X~^T H X~    Gram, reduced in FP64, copied to the host
+//   host: D = diag(S~)^(1/2) (deferred normalization of eq. PCAL-main),
+//         S = D^-1 S~ D^-1, Lambda0 = D^-1 L~ D^-1, fea, the eq. lambda2
+//         multiplier Lambda, C = beta (S - I) - Lambda, C' = -Lambda0
+//   G = HX + BX C, R = HX + BX C'     (X = X~ D^-1; R gives kkt)
+//   stopping test (Section 4.1)
+//   P = T^-1 G by Jacobi-PCG (paper preconditioner) | s .* G (learned) | G
+//   BB2 step (Section 4.4) from <S,Y>, <Y,Y>
+//   X~ <- X - P / eta ;  X^{k-1} <- X
+// The p x p algebra is FP64 on the host; everything n-sized runs in the
+// kernels of k_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ofks.h"
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace ofks {
+// launchers (k_spmm.hip)
+template <typename T>
+hipError_t launch_spmm_pair(hipStream_t, int64_t, int, const int64_t *, const int32_t *, const void *, const T *,
+                            T *, T *, int);
+template <typename T>
+hipError_t launch_spmm_shift(hipStream_t, int, int64_t, int, const int64_t *, const int32_t *, const void *,
+                             const T *, const uint8_t *, const T *, T *, double *);
+hipError_t launch_spmv_dot(hipStream_t, int, int64_t, const int64_t *, const int32_t *, const double *,
+                           const double *, double *, double *);
+// (k_blas.hip)
+struct GradArgs {
+    const void *HX;
+    void *P;
+    void *R;
+    void *D;
+    const double *lhd;
+    const double *bd;
+    const void *lam;
+    const uint8_t *active;
+    double *part;
+};
+enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2 };
+template <typename T>
+hipError_t launch_gram(hipStream_t, int64_t, int, int, const T *, const T *, const T *, double *, int *);
+hipError_t launch_colsum(hipStream_t, int64_t, int64_t, const double *, double *);
+template <typename T>
+hipError_t launch_rowgemm(hipStream_t, int, int64_t, int, int, int, const T *, const T *, const T *, T *,
+                          GradArgs, int *);
+template <typename T>
+hipError_t launch_pcg_xr(hipStream_t, int, int64_t, int, int, const T *, const uint8_t *, const double *,
+                         const double *, const T *, const T *, const T *, T *, T *, double *);
+template <typename T>
+hipError_t launch_coldot(hipStream_t, int, int64_t, int, const T *, const T *, double *);
+template <typename T>
+hipError_t launch_bbdot(hipStream_t, int, int64_t, int, const T *, const T *, const T *, const T *, const T *,
+                        double *);
+template <typename T>
+hipError_t launch_pcg_dir(hipStream_t, int64_t, int, const T *, const uint8_t *, const double *, const double *,
+                          const T *, const T *, T *);
+template <typename T>
+hipError_t launch_update_b(hipStream_t, int64_t, int, const T *, T, const T *, T *, T *);
+template <typename T>
+hipError_t launch_pcg_scalars(hipStream_t, int, int, const double *, double *, T *);
+template <typename S, typename D>
+hipError_t launch_convert(hipStream_t, int64_t, const S *, D *);
+template <typename S, typename D>
+hipError_t launch_scale_copy(hipStream_t, int64_t, int, const S *, const S *, D *);
+template <typename T>
+hipError_t launch_pcg_init(hipStream_t, int, int64_t, int, const uint8_t *, const double *, const double *,
+                           const T *, const T *, T *, T *, T *, double *);
+// (k_mesh.hip)
+hipError_t scan_exclusive(hipStream_t, int64_t, const int32_t *, int64_t *, int64_t *);
+hipError_t launch_interior_flags(hipStream_t, int64_t, const uint8_t *, int32_t *);
+hipError_t launch_dof(hipStream_t, int64_t, const uint8_t *, const int64_t *, int32_t *);
+hipError_t launch_inc_count(hipStream_t, int64_t, const int32_t *, int32_t *);
+hipError_t launch_inc_fill(hipStream_t, int64_t, const int32_t *, const int64_t *, int32_t *, int32_t *);
+hipError_t launch_inc_sort(hipStream_t, int64_t, const int64_t *, int32_t *, int32_t *);
+hipError_t launch_row_pattern(hipStream_t, int64_t, int, const int32_t *, const int64_t *, const int32_t *,
+                              const int32_t *, int32_t *, const int64_t *, int32_t *, int32_t *);
+hipError_t launch_tet_geom(hipStream_t, int64_t, const double *, const int32_t *, double *, int32_t *);
+hipError_t launch_vext(hipStream_t, int64_t, const double *, const int32_t *, int, const double *,
+                       const double *, double *);
+hipError_t launch_assemble(hipStream_t, int64_t, int, const int32_t *, const int64_t *, const int32_t *,
+                           const int32_t *, const double *, const double *, const int64_t *, const int32_t *,
+                           double *, double *, double *, double2 *, double2 *, double *, double *, double *);
+hipError_t launch_pairs_to_f32(hipStream_t, int64_t, const double2 *, float2 *);
+hipError_t launch_split_pairs(hipStream_t, int64_t, const double2 *, double *, double *);
+hipError_t launch_make_pairs(hipStream_t, int64_t, const double *, const double *, double2 *);
+hipError_t launch_diag(hipStream_t, int64_t, const int64_t *, const int32_t *, const double2 *, double *, double *,
+                       int32_t *);
+// (k_density.hip)
+template <typename T>
+hipError_t launch_density_xc(hipStream_t, int, int64_t, int, const int32_t *, const int32_t *, const double *,
+                             const T *, const T *, double, double *, double *, double *, double *);
+hipError_t launch_load_vec(hipStream_t, int64_t, const int32_t *, const int64_t *, const int32_t *,
+                           const double *, const double *, double *);
+hipError_t launch_veff(hipStream_t, int64_t, const int32_t *, const int32_t *, const double *, const double *,
+                       const double *, double *);
+hipError_t launch_cg_start(hipStream_t, int, int64_t, double, const double *, const double *, const double *,
+                           double *, double *, double *, double *);
+hipError_t launch_cg_alpha(hipStream_t, int, const double *, double *);
+hipError_t launch_cg_xr(hipStream_t, int, int64_t, const double *, const double *, const double *,
+                        const double *, double *, double *, double *);
+hipError_t launch_cg_dir(hipStream_t, int, int64_t, const double *, const double *, const double *, double *);
+hipError_t launch_dot(hipStream_t, int, int64_t, const double *, const double *, double *);
+}  // namespace ofks
+
+using namespace ofks;
+
+namespace {
+
+struct ErrorOut {
+    int code;
+};
+
+template <typename T> struct Blocks {
+    T *Xt = nullptr, *Xp = nullptr, *P = nullptr, *Pp = nullptr, *HX = nullptr, *BX = nullptr, *R = nullptr,
+      *D = nullptr;
+    T *dinv = nullptr, *CC = nullptr, *lam = nullptr, *alpha = nullptr, *beta = nullptr;
+};
+
+struct Timer {
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+
+}  // namespace
+
+struct ofks_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    std::vector<void *> allocs;
+
+    // state
+    bool has_mesh = false, has_nuclei = false, has_system = false, assembled = false, has_lhalf = false;
+    bool has_params = false, has_x = false, done = false;
+    ofks_params prm{};
+
+    // mesh
+    int64_t n_nodes = 0, n_tets = 0;
+    double *xyz = nullptr, *geom = nullptr, *vext_q = nullptr;
+    int32_t *tets = nullptr, *dof = nullptr, *inc = nullptr;
+    int64_t *iptr = nullptr;
+    uint8_t *dir = nullptr;
+    int M = 0;
+    std::vector<double> Zh, Rh;
+    double *Zd = nullptr, *Rd = nullptr;
+    double Enuc = 0.0;
+
+    // system
+    int64_t n = 0, nnz = 0;
+    int64_t *rp = nullptr;
+    int32_t *col = nullptr;
+    double *Lv = nullptr, *Bv = nullptr, *Mv = nullptr, *lhd = nullptr, *bd = nullptr, *hd = nullptr,
+           *Ldiag = nullptr;
+    double2 *hb = nullptr, *lb = nullptr;
+    float2 *hb32 = nullptr, *lb32 = nullptr;
+
+    // SCF work
+    double *rho_q = nullptr, *eps_q = nullptr, *vxc_q = nullptr, *veff_q = nullptr, *bvec = nullptr,
+           *U = nullptr, *cg_r = nullptr, *cg_d = nullptr, *cg_q = nullptr, *cg_sc = nullptr;
+    double scf_parts[4] = {0, 0, 0, 0};  // int rho, int eps rho, int vxc rho, U.b/2
+
+    // iteration
+    int p = 0;
+    int prec = OFKS_F64;
+    Blocks<double> b64;
+    Blocks<float> b32;
+    uint8_t *active = nullptr;
+    double *part = nullptr, *red = nullptr, *rz = nullptr;
+    size_t part_cap = 0;
+    double *hbuf = nullptr;  // pinned host buffer for downloads
+    size_t hbuf_cap = 0;
+    char *hup = nullptr;     // pinned upload staging, consumed by a cursor reset at each sync
+    size_t hup_cap = 0, hup_off = 0;
+    int grid = 1024;         // persistent grid for partial-sum kernels
+    int gemm_rows = 1024;
+
+    int k = 0;
+    double kkt0 = -1.0, eta = 0.0, eta0 = 0.0;
+    bool have_prev = false;
+    std::vector<double> dinv_h, S, L0;
+    double last_kkt = NAN, last_fea = NAN, last_rel = NAN, last_energy = NAN;
+    bool dinv_from_scf = false;
+    // learned form bookkeeping
+    std::vector<double> ehist;
+
+    // timing
+    bool timing = false;
+    std::map<std::string, Timer> timers;
+    struct Pending {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> evpool;
+};
+
+namespace {
+
+int fail(ofks_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(...)                                                                                 \
+    do {                                                                                            \
+        hipError_t e_ = (__VA_ARGS__);                                                              \
+        if (e_ != hipSuccess) return fail(c, OFKS_EHIP, "%s: %s (%s:%d)", #__VA_ARGS__,              \
+                                          hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+#define CHK(...)                   \
+    do {                           \
+        int r_ = (__VA_ARGS__);    \
+        if (r_ < 0) return r_;     \
+    } while (0)
+
+template <typename T> int dalloc(ofks_ctx *c, T **out, size_t count) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(c, OFKS_EHIP, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    c->allocs.push_back(p);
+    *out = (T *)p;
+    return OFKS_OK;
+}
+
+template <typename T> void dfree(ofks_ctx *c, T *&ptr) {
+    if (!ptr) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), (void *)ptr);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree((void *)ptr);
+    ptr = nullptr;
+}
+
+int ensure_host(ofks_ctx *c, size_t doubles) {
+    if (c->hbuf_cap >= doubles) return OFKS_OK;
+    if (c->hbuf) (void)hipHostFree(c->hbuf);
+    c->hbuf = nullptr;
+    hipError_t e = hipHostMalloc((void **)&c->hbuf, doubles * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(c, OFKS_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+    c->hbuf_cap = doubles;
+    return OFKS_OK;
+}
+
+int ensure_part(ofks_ctx *c, size_t doubles) {
+    if (c->part_cap >= doubles) return OFKS_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));   // kernels in flight may still use the old buffer
+    dfree(c, c->part);
+    CHK(dalloc(c, &c->part, doubles));
+    c->part_cap = doubles;
+    return OFKS_OK;
+}
+
+// --- timing -----------------------------------------------------------------
+hipEvent_t get_event(ofks_ctx *c) {
+    if (!c->evpool.empty()) {
+        hipEvent_t e = c->evpool.back();
+        c->evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Scope {
+    ofks_ctx *c;
+    const char *name;
+    hipEvent_t a = nullptr;
+    Scope(ofks_ctx *c_, const char *n) : c(c_), name(n) {
+        if (c->timing) {
+            a = get_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~Scope() {
+        if (c->timing && a) {
+            hipEvent_t b = get_event(c);
+            if (b) {
+                (void)hipEventRecord(b, c->stream);
+                c->pending.push_back({name, a, b});
+            }
+        }
+    }
+};
+
+void resolve_timers(ofks_ctx *c) {
+    for (auto &pd : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+            auto &t = c->timers[pd.name];
+            t.ms += ms;
+            t.launches += 1;
+        }
+        c->evpool.push_back(pd.a);
+        c->evpool.push_back(pd.b);
+    }
+    c->pending.clear();
+}
+
+int sync(ofks_ctx *c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->hup_off = 0;
+    if (c->timing) resolve_timers(c);
+    return OFKS_OK;
+}
+
+template <typename T> Blocks<T> &blk(ofks_ctx *c);
+template <> Blocks<double> &blk<double>(ofks_ctx *c) { return c->b64; }
+template <> Blocks<float> &blk<float>(ofks_ctx *c) { return c->b32; }
+template <typename T> const void *hbT(ofks_ctx *c);
+template <> const void *hbT<double>(ofks_ctx *c) { return c->hb; }
+template <> const void *hbT<float>(ofks_ctx *c) { return c->hb32; }
+template <typename T> const void *lbT(ofks_ctx *c);
+template <> const void *lbT<double>(ofks_ctx *c) { return c->lb; }
+template <> const void *lbT<float>(ofks_ctx *c) { return c->lb32; }
+
+template <typename T> int alloc_blocks(ofks_ctx *c) {
+    Blocks<T> &b = blk<T>(c);
+    const size_t np = (size_t)c->n * c->p;
+    CHK(dalloc(c, &b.Xt, np));
+    CHK(dalloc(c, &b.Xp, np));
+    CHK(dalloc(c, &b.P, np));
+    CHK(dalloc(c, &b.Pp, np));
+    CHK(dalloc(c, &b.HX, np));
+    CHK(dalloc(c, &b.BX, np));
+    CHK(dalloc(c, &b.R, np));
+    CHK(dalloc(c, &b.D, np));
+    CHK(dalloc(c, &b.dinv, c->p));
+    CHK(dalloc(c, &b.CC, (size_t)c->p * 2 * c->p));
+    CHK(dalloc(c, &b.lam, c->p));
+    CHK(dalloc(c, &b.alpha, c->p));
+    CHK(dalloc(c, &b.beta, c->p));
+    return OFKS_OK;
+}
+
+template <typename T> void free_blocks(ofks_ctx *c) {
+    Blocks<T> &b = blk<T>(c);
+    dfree(c, b.Xt);
+    dfree(c, b.Xp);
+    dfree(c, b.P);
+    dfree(c, b.Pp);
+    dfree(c, b.HX);
+    dfree(c, b.BX);
+    dfree(c, b.R);
+    dfree(c, b.D);
+    dfree(c, b.dinv);
+    dfree(c, b.CC);
+    dfree(c, b.lam);
+    dfree(c, b.alpha);
+    dfree(c, b.beta);
+}
+
+// stage bytes in pinned memory and enqueue the copy; the staging region is
+// not reused before the next sync, so no wait is needed here
+int upload_bytes(ofks_ctx *c, void *dst, const void *src, size_t bytes) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (c->hup_off + need > c->hup_cap) {
+        CHK(sync(c));
+        if (need > c->hup_cap) {
+            if (c->hup) (void)hipHostFree(c->hup);
+            c->hup = nullptr;
+            const size_t cap = std::max<size_t>(need, size_t(1) << 20);
+            hipError_t e = hipHostMalloc((void **)&c->hup, cap, hipHostMallocDefault);
+            if (e != hipSuccess) return fail(c, OFKS_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+            c->hup_cap = cap;
+        }
+    }
+    char *h = c->hup + c->hup_off;
+    std::memcpy(h, src, bytes);
+    c->hup_off += need;
+    HIPCHK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, c->stream));
+    return OFKS_OK;
+}
+
+// upload host doubles as T
+template <typename T> int upload(ofks_ctx *c, T *dst, const std::vector<double> &src) {
+    std::vector<T> tmp(src.begin(), src.end());
+    return upload_bytes(c, dst, tmp.data(), tmp.size() * sizeof(T));
+}
+
+int download(ofks_ctx *c, std::vector<double> &dst, const double *src, size_t count) {
+    CHK(ensure_host(c, count));
+    HIPCHK(hipMemcpyAsync(c->hbuf, src, count * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    dst.assign(c->hbuf, c->hbuf + count);
+    return OFKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gram: S~ = X^T BX, L~ = X^T HX (host, FP64, not symmetrized)
+// ---------------------------------------------------------------------------
+template <typename T>
+int gram(ofks_ctx *c, const T *X, const T *BX, const T *HX, std::vector<double> &St, std::vector<double> &Lt) {
+    const int p = c->p;
+    const size_t pp2 = (size_t)p * 2 * p;
+    // launch_gram uses at most max(target, tiles) * 64 * 64 partial values
+    const int target = 2048;
+    CHK(ensure_part(c, std::max<size_t>(pp2, (size_t)target * 64 * 64)));
+    int ns = 0;
+    {
+        Scope sc(c, "gram");
+        HIPCHK(launch_gram<T>(c->stream, c->n, p, target, X, BX, HX, c->part, &ns));
+    }
+    if ((size_t)ns * pp2 > c->part_cap) return fail(c, OFKS_EINVAL, "gram: partial buffer too small");
+    HIPCHK(launch_colsum(c->stream, ns, (int64_t)pp2, c->part, c->red));
+    std::vector<double> G;
+    CHK(download(c, G, c->red, pp2));
+    St.assign((size_t)p * p, 0.0);
+    Lt.assign((size_t)p * p, 0.0);
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            St[a * p + b] = G[(size_t)a * 2 * p + b];
+            Lt[a * p + b] = G[(size_t)a * 2 * p + p + b];
+        }
+    return OFKS_OK;
+}
+
+// column sums of A .* B over rows (FP64)
+template <typename T> int coldot(ofks_ctx *c, const T *A, const T *B, std::vector<double> &out) {
+    CHK(ensure_part(c, (size_t)c->grid * c->p));
+    HIPCHK(launch_coldot<T>(c->stream, c->grid, c->n, c->p, A, B, c->part));
+    HIPCHK(launch_colsum(c->stream, c->grid, c->p, c->part, c->red));
+    return download(c, out, c->red, c->p);
+}
+
+// ---------------------------------------------------------------------------
+// SCF: H(X) for X = Xs .* dinv (Section 2.2)
+// ---------------------------------------------------------------------------
+int poisson(ofks_ctx *c) {
+    const int64_t n = c->n;
+    const int g = 512;
+    CHK(ensure_part(c, (size_t)3 * g));
+    {
+        Scope sc(c, "poisson");
+        HIPCHK(launch_spmv_dot(c->stream, g, n, c->rp, c->col, c->Lv, c->U, c->cg_q, c->part));
+        // Jacobi preconditioner diag(L/2): a constant multiple of diag(L) leaves the CG iterates unchanged
+        HIPCHK(launch_cg_start(c->stream, g, n, 4.0 * M_PI, c->bvec, c->cg_q, c->lhd, c->cg_r, c->cg_d, c->part,
+                               c->cg_sc));
+    }
+    std::vector<double> sc;
+    CHK(download(c, sc, c->cg_sc, 3));
+    double rr = sc[1], bb = sc[2];
+    const double tol2 = c->prm.poisson_rtol * c->prm.poisson_rtol * bb;
+    int it = 0;
+    while (rr > tol2 && it < c->prm.poisson_max_iter) {
+        {
+            Scope s2(c, "poisson");
+            for (int j = 0; j < 10; ++j) {
+                HIPCHK(launch_spmv_dot(c->stream, g, n, c->rp, c->col, c->Lv, c->cg_d, c->cg_q, c->part));
+                HIPCHK(launch_cg_alpha(c->stream, g, c->part, c->cg_sc));
+                HIPCHK(launch_cg_xr(c->stream, g, n, c->cg_sc, c->cg_d, c->cg_q, c->lhd, c->U, c->cg_r, c->part));
+                HIPCHK(launch_cg_dir(c->stream, g, n, c->cg_sc, c->cg_r, c->lhd, c->cg_d));
+            }
+        }
+        it += 10;
+        CHK(download(c, sc, c->cg_sc, 2));
+        rr = sc[1];
+        if (!std::isfinite(rr)) return fail(c, OFKS_ENONFINITE, "Hartree CG diverged");
+    }
+    if (rr > tol2) return fail(c, OFKS_NOT_CONVERGED, "Hartree CG did not reach %g", c->prm.poisson_rtol);
+    return OFKS_OK;
+}
+
+template <typename T> int build_h(ofks_ctx *c, const T *X, const T *dinv_dev) {
+    const int64_t nt = c->n_tets;
+    const int g = 1024;
+    CHK(ensure_part(c, (size_t)3 * g));
+    {
+        Scope sc(c, "density");
+        HIPCHK(launch_density_xc<T>(c->stream, g, nt, c->p, c->tets, c->dof, c->geom, X, dinv_dev,
+                                    c->prm.occupation, c->rho_q, c->eps_q, c->vxc_q, c->part));
+    }
+    HIPCHK(launch_colsum(c->stream, g, 3, c->part, c->red));
+    std::vector<double> s3;
+    CHK(download(c, s3, c->red, 3));
+    {
+        Scope sc(c, "density");
+        HIPCHK(launch_load_vec(c->stream, c->n_nodes, c->dof, c->iptr, c->inc, c->geom, c->rho_q, c->bvec));
+    }
+    int rc = poisson(c);
+    if (rc != OFKS_OK) return rc < 0 ? rc : fail(c, OFKS_ENONFINITE, "%s", c->err.c_str());
+    HIPCHK(launch_dot(c->stream, 512, c->n, c->U, c->bvec, c->part));
+    HIPCHK(launch_colsum(c->stream, 512, 1, c->part, c->red));
+    std::vector<double> ub;
+    CHK(download(c, ub, c->red, 1));
+    c->scf_parts[0] = s3[0];
+    c->scf_parts[1] = s3[1];
+    c->scf_parts[2] = s3[2];
+    c->scf_parts[3] = 0.5 * ub[0];
+    {
+        Scope sc(c, "assemble_h");
+        HIPCHK(launch_veff(c->stream, nt, c->tets, c->dof, c->U, c->vext_q, c->vxc_q, c->veff_q));
+        HIPCHK(launch_assemble(c->stream, c->n_nodes, 1, c->dof, c->iptr, c->inc, c->tets, c->geom, c->veff_q,
+                               c->rp, c->col, c->Lv, nullptr, nullptr, c->hb, nullptr, nullptr, nullptr, c->hd));
+        if (c->hb32) HIPCHK(launch_pairs_to_f32(c->stream, c->nnz, c->hb, c->hb32));
+    }
+    return OFKS_OK;
+}
+
+double bb_eta(int rule, int k, double sy, double yy, double ss, double eta_prev, double eta0) {
+    if (rule == OFKS_STEP_FIXED) return eta0;
+    double num, den;
+    const bool bb1 = rule == OFKS_STEP_BB1 || (rule == OFKS_STEP_ABB1 && k % 2 == 1) ||
+                     (rule == OFKS_STEP_ABB2 && k % 2 == 0);
+    if (bb1) { num = std::fabs(sy); den = ss; }
+    else { num = yy; den = std::fabs(sy); }
+    if (!(den > 0.0) || !std::isfinite(num) || !std::isfinite(den)) return eta_prev;
+    double e = num / den;
+    if (!(e > 0.0) || !std::isfinite(e)) return eta_prev;
+    return std::min(std::max(e, 1e-8 * eta0), 1e8 * eta0);
+}
+
+// ---------------------------------------------------------------------------
+// one PCAL iteration
+// ---------------------------------------------------------------------------
+template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) {
+    Blocks<T> &B = blk<T>(c);
+    const int p = c->p;
+    const int64_t n = c->n;
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool scf = c->prm.scf != 0;
+
+    // [SCF] normalize and rebuild H(X^k)
+    if (scf) {
+        std::vector<double> dn(p, 1.0);
+        if (c->k > 0) {
+            {
+                Scope sc(c, "spmm_dual");
+                HIPCHK(launch_spmm_pair<T>(c->stream, n, p, c->rp, c->col, hbT<T>(c), B.Xt, B.BX, nullptr, 1));
+            }
+            std::vector<double> d2;
+            CHK(coldot<T>(c, B.Xt, B.BX, d2));
+            for (int i = 0; i < p; ++i) {
+                if (!(d2[i] > 0.0)) return fail(c, OFKS_EZERONORM, "column %d has zero B-norm", i);
+                dn[i] = 1.0 / std::sqrt(d2[i]);
+            }
+        }
+        c->dinv_h = dn;
+        CHK(upload<T>(c, B.dinv, dn));
+        CHK(build_h<T>(c, B.Xt, B.dinv));
+    }
+
+    // HX~, BX~
+    {
+        Scope sc(c, "spmm_dual");
+        HIPCHK(launch_spmm_pair<T>(c->stream, n, p, c->rp, c->col, hbT<T>(c), B.Xt, B.HX, B.BX, 0));
+    }
+    std::vector<double> St, Lt;
+    CHK(gram<T>(c, B.Xt, B.BX, B.HX, St, Lt));
+
+    // deferred normalization
+    std::vector<double> &dn = c->dinv_h;
+    if (!scf) {
+        dn.assign(p, 1.0);
+        if (c->k > 0)
+            for (int i = 0; i < p; ++i) {
+                if (!(St[i * p + i] > 0.0)) return fail(c, OFKS_EZERONORM, "column %d has zero B-norm", i);
+                dn[i] = 1.0 / std::sqrt(St[i * p + i]);
+            }
+    }
+    std::vector<double> S(p * p), L0(p * p);
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            S[a * p + b] = 0.5 * (St[a * p + b] + St[b * p + a]) * dn[a] * dn[b];
+            L0[a * p + b] = 0.5 * (Lt[a * p + b] + Lt[b * p + a]) * dn[a] * dn[b];
+        }
+    for (double v : S)
+        if (!std::isfinite(v)) return fail(c, OFKS_ENONFINITE, "non-finite X^T B X");
+    for (double v : L0)
+        if (!std::isfinite(v)) return fail(c, OFKS_ENONFINITE, "non-finite X^T H X");
+    double fea = 0.0;
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            const double e = S[a * p + b] - (a == b ? 1.0 : 0.0);
+            fea += e * e;
+        }
+    fea = std::sqrt(fea);
+    const double beta = c->prm.beta;
+    // eq. lambda2: only the diagonal of Lambda0 - S Lambda0 + beta S (S - I) is needed
+    std::vector<double> lam_diag(p);
+    std::vector<double> CC((size_t)p * 2 * p);
+    for (int i = 0; i < p; ++i) {
+        double sl = 0.0, ss = 0.0;
+        for (int k2 = 0; k2 < p; ++k2) {
+            sl += S[i * p + k2] * L0[k2 * p + i];
+            ss += S[i * p + k2] * (S[k2 * p + i] - (k2 == i ? 1.0 : 0.0));
+        }
+        lam_diag[i] = L0[i * p + i] + (L0[i * p + i] - sl + beta * ss);
+    }
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            const double lam_ab = (a == b) ? lam_diag[a] : L0[a * p + b];
+            CC[(size_t)a * 2 * p + b] = beta * (S[a * p + b] - (a == b ? 1.0 : 0.0)) - lam_ab;
+            CC[(size_t)a * 2 * p + p + b] = -L0[a * p + b];
+        }
+    c->S = S;
+    c->L0 = L0;
+
+    const bool pcg = c->prm.precond == OFKS_PRECOND_PAPER;
+    std::vector<double> shift(p, 0.0);
+    std::vector<uint8_t> act(p, 0);
+    bool any_active = false;
+    for (int i = 0; i < p; ++i) {
+        const double li = c->prm.precond_lambda == 0 ? lam_diag[i] : L0[i * p + i];
+        shift[i] = li;
+        act[i] = (pcg && li < 0.0) ? 1 : 0;
+        any_active |= act[i] != 0;
+    }
+    if (!scf) CHK(upload<T>(c, B.dinv, dn));
+    CHK(upload<T>(c, B.CC, CC));
+    CHK(upload<T>(c, B.lam, shift));
+    CHK(upload_bytes(c, c->active, act.data(), p));
+
+    // G, R (kkt) and the start of the CG
+    GradArgs ga{B.HX, B.P, B.R, B.D, c->lhd, c->bd, B.lam, c->active, c->part};
+    int gx = 0;
+    const int epi = any_active ? EPI_GRAD_PCG : EPI_GRAD;
+    {
+        const int tc = (2 * p <= 16) ? 16 : ((2 * p <= 32) ? 32 : 64);
+        const int gy = (2 * p + tc - 1) / tc;
+        CHK(ensure_part(c, (size_t)c->gemm_rows * gy * (1 + p)));
+        {
+            Scope sc(c, "update_a");
+            HIPCHK(launch_rowgemm<T>(c->stream, epi, n, p, 2 * p, c->gemm_rows, B.BX, B.dinv, B.CC, nullptr, ga,
+                                     &gx));
+        }
+        HIPCHK(launch_colsum(c->stream, (int64_t)gx * gy, 1 + p, c->part, c->red));
+    }
+    std::vector<double> r2;
+    CHK(download(c, r2, c->red, 1 + p));
+    const double kkt = std::sqrt(std::max(0.0, r2[0]));
+    if (c->kkt0 < 0) c->kkt0 = kkt;
+    const double rel = (kkt + fea) / c->kkt0;
+    double energy = NAN;
+    const int ee = std::max(1, c->prm.energy_every);
+    if (scf) {
+        double trl = 0.0;
+        for (int i = 0; i < p; ++i) trl += L0[i * p + i];
+        energy = c->prm.occupation * trl - c->scf_parts[3] - c->scf_parts[2] + c->scf_parts[1] + c->Enuc;
+    } else if (c->k % ee == 0) {
+        double tr;
+        if (dense::trace_sinv_a(S, L0, p, tr)) energy = tr;
+    }
+    c->last_kkt = kkt;
+    c->last_fea = fea;
+    c->last_rel = rel;
+    c->last_energy = energy;
+    if (st) {
+        st->k = c->k;
+        st->kkt = kkt;
+        st->fea = fea;
+        st->rel = rel;
+        st->energy = energy;
+        st->eta = c->eta;
+        st->precision = std::is_same<T, double>::value ? OFKS_F64 : OFKS_F32;
+        st->precond_used = c->prm.precond;
+        st->fell_back = 0;
+    }
+    if (!std::isfinite(rel)) return fail(c, OFKS_ENONFINITE, "non-finite residual");
+    if (rel < c->prm.tol || c->k >= c->prm.max_iter) {
+        *stop = true;
+        if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return OFKS_OK;
+    }
+
+    // preconditioner: columnwise Jacobi-PCG from zero, fixed iteration count
+    if (any_active) {
+        HIPCHK(hipMemcpyAsync(c->rz, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        CHK(ensure_part(c, (size_t)c->grid * p));
+        for (int it = 0; it < c->prm.pcg_iters; ++it) {
+            {
+                Scope sc(c, "spmm_shift");
+                HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, n, p, c->rp, c->col, lbT<T>(c), B.lam, c->active,
+                                            B.D, B.HX, c->part));
+            }
+            HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+            HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, c->rz, B.alpha));
+            {
+                Scope sc(c, "pcg_axpy");
+                HIPCHK(launch_pcg_xr<T>(c->stream, c->grid, n, p, it == 0, B.alpha, c->active, c->lhd, c->bd,
+                                        B.lam, B.D, B.HX, B.P, B.R, c->part));
+            }
+            HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+            if (it + 1 < c->prm.pcg_iters) {
+                HIPCHK(launch_pcg_scalars<T>(c->stream, p, 1, c->red, c->rz, B.beta));
+                Scope sc(c, "pcg_axpy");
+                HIPCHK(launch_pcg_dir<T>(c->stream, n, p, B.beta, c->active, c->lhd, c->bd, B.lam, B.R, B.D));
+            }
+        }
+    }
+
+    // BB step
+    CHK(ensure_part(c, (size_t)c->grid * 5));
+    {
+        Scope sc(c, "bbdot");
+        HIPCHK(launch_bbdot<T>(c->stream, c->grid, n, p, B.Xt, B.dinv, B.P, c->have_prev ? B.Xp : nullptr,
+                               c->have_prev ? B.Pp : nullptr, c->part));
+    }
+    HIPCHK(launch_colsum(c->stream, c->grid, 5, c->part, c->red));
+    std::vector<double> s5;
+    CHK(download(c, s5, c->red, 5));
+    if (!c->have_prev) {
+        if (c->eta0 <= 0.0) c->eta0 = c->prm.eta0 > 0 ? c->prm.eta0 : std::sqrt(s5[3]) / std::sqrt(s5[4]);
+        if (c->eta <= 0.0) c->eta = c->eta0;
+    } else {
+        c->eta = bb_eta(c->prm.step_rule, c->k, s5[0], s5[1], s5[2], c->eta, c->eta0);
+    }
+    if (!(c->eta > 0.0) || !std::isfinite(c->eta)) return fail(c, OFKS_ENONFINITE, "bad step parameter");
+
+    {
+        Scope sc(c, "update_b");
+        HIPCHK(launch_update_b<T>(c->stream, n, p, B.dinv, (T)c->eta, B.P, B.Xt, B.Xp));
+    }
+    std::swap(B.P, B.Pp);
+    c->have_prev = true;
+    c->k += 1;
+    CHK(sync(c));
+    if (st) {
+        st->eta = c->eta;
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return OFKS_OK;
+}
+
+// switch the iteration from FP32 to FP64 blocks (refinement sweeps)
+int promote_to_f64(ofks_ctx *c) {
+    CHK(alloc_blocks<double>(c));
+    HIPCHK(launch_convert<float, double>(c->stream, c->n * (int64_t)c->p, c->b32.Xt, c->b64.Xt));
+    HIPCHK(launch_convert<float, double>(c->stream, c->n * (int64_t)c->p, c->b32.Xp, c->b64.Xp));
+    HIPCHK(launch_convert<float, double>(c->stream, c->n * (int64_t)c->p, c->b32.Pp, c->b64.Pp));
+    CHK(sync(c));
+    free_blocks<float>(c);
+    c->prec = OFKS_F64;
+    return OFKS_OK;
+}
+
+int check_ready(ofks_ctx *c) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "no system: call ofks_assemble or ofks_csr_load");
+    if (!c->has_params) return fail(c, OFKS_ESTATE, "call ofks_set_params first");
+    if (!c->has_x) return fail(c, OFKS_ESTATE, "call ofks_set_x0 first");
+    return OFKS_OK;
+}
+
+int ensure_f32_matrices(ofks_ctx *c) {
+    if (!c->hb32) {
+        CHK(dalloc(c, &c->hb32, c->nnz));
+        CHK(dalloc(c, &c->lb32, c->nnz));
+    }
+    HIPCHK(launch_pairs_to_f32(c->stream, c->nnz, c->hb, c->hb32));
+    HIPCHK(launch_pairs_to_f32(c->stream, c->nnz, c->lb, c->lb32));
+    return OFKS_OK;
+}
+
+int alloc_system_common(ofks_ctx *c) {
+    CHK(dalloc(c, &c->lhd, c->n));
+    CHK(dalloc(c, &c->bd, c->n));
+    CHK(dalloc(c, &c->hd, c->n));
+    CHK(dalloc(c, &c->red, 2 * 1024 * 1024 + 64));   // p x 2p partial sums for p <= 1024
+    return OFKS_OK;
+}
+
+void free_system(ofks_ctx *c) {
+    dfree(c, c->rp);
+    dfree(c, c->col);
+    dfree(c, c->Lv);
+    dfree(c, c->Bv);
+    dfree(c, c->Mv);
+    dfree(c, c->hb);
+    dfree(c, c->lb);
+    dfree(c, c->hb32);
+    dfree(c, c->lb32);
+    dfree(c, c->lhd);
+    dfree(c, c->bd);
+    dfree(c, c->hd);
+    dfree(c, c->Ldiag);
+    dfree(c, c->red);
+    c->has_system = false;
+    c->assembled = false;
+    c->has_lhalf = false;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void ofks_default_params(ofks_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->beta = 1.0;
+    p->eta0 = 0.0;
+    p->tol = 1e-8;
+    p->step_rule = OFKS_STEP_BB2;
+    p->precond = OFKS_PRECOND_PAPER;
+    p->pcg_iters = 10;
+    p->precision = OFKS_F64;
+    p->precond_lambda = 0;
+    p->max_iter = 1000;
+    p->occupation = 2.0;
+    p->scf = 0;
+    p->energy_every = 1;
+    p->refine_tol = 0.0;
+    p->poisson_rtol = 1e-12;
+    p->poisson_max_iter = 20000;
+    p->fallback_window = 5;
+    p->fallback_hold = 20;
+}
+
+int ofks_create(ofks_ctx **out, void *hip_stream) {
+    if (!out) return OFKS_EINVAL;
+    ofks_ctx *c = new ofks_ctx();
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return OFKS_EHIP;
+    }
+    ofks_default_params(&c->prm);
+    *out = c;
+    return OFKS_OK;
+}
+
+int ofks_destroy(ofks_ctx *c) {
+    if (!c) return OFKS_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->hbuf) (void)hipHostFree(c->hbuf);
+    if (c->hup) (void)hipHostFree(c->hup);
+    for (auto &pd : c->pending) {
+        (void)hipEventDestroy(pd.a);
+        (void)hipEventDestroy(pd.b);
+    }
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    delete c;
+    return OFKS_OK;
+}
+
+const char *ofks_last_error(const ofks_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int ofks_mesh_load(ofks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tets,
+                   const uint8_t *dirichlet) {
+    if (!c) return OFKS_EINVAL;
+    if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tets || !dirichlet)
+        return fail(c, OFKS_EINVAL, "mesh_load: empty mesh or null pointer");
+    if (n_nodes >= (int64_t(1) << 31) || n_tets >= (int64_t(1) << 29))
+        return fail(c, OFKS_ECAPACITY, "mesh_load: mesh too large for 32-bit indices");
+    for (int64_t i = 0; i < 4 * n_tets; ++i)
+        if (tets[i] < 0 || tets[i] >= n_nodes) return fail(c, OFKS_EINVAL, "mesh_load: node index out of range");
+    dfree(c, c->xyz);
+    dfree(c, c->tets);
+    dfree(c, c->dir);
+    CHK(dalloc(c, &c->xyz, 3 * n_nodes));
+    CHK(dalloc(c, &c->tets, 4 * n_tets));
+    CHK(dalloc(c, &c->dir, n_nodes));
+    HIPCHK(hipMemcpyAsync(c->xyz, xyz, 3 * n_nodes * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->tets, tets, 4 * n_tets * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->dir, dirichlet, n_nodes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->n_nodes = n_nodes;
+    c->n_tets = n_tets;
+    c->has_mesh = true;
+    c->has_x = false;
+    return OFKS_OK;
+}
+
+int ofks_nuclei_set(ofks_ctx *c, int32_t M, const double *Z, const double *R) {
+    if (!c) return OFKS_EINVAL;
+    if (M < 0 || (M > 0 && (!Z || !R))) return fail(c, OFKS_EINVAL, "nuclei_set: bad arguments");
+    c->M = M;
+    c->Zh.assign(Z, Z + M);
+    c->Rh.assign(R, R + 3 * M);
+    dfree(c, c->Zd);
+    dfree(c, c->Rd);
+    CHK(dalloc(c, &c->Zd, std::max(M, 1)));
+    CHK(dalloc(c, &c->Rd, 3 * std::max(M, 1)));
+    if (M > 0) {
+        HIPCHK(hipMemcpy(c->Zd, Z, M * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->Rd, R, 3 * M * sizeof(double), hipMemcpyHostToDevice));
+    }
+    double e = 0.0;
+    for (int j = 0; j < M; ++j)
+        for (int k = j + 1; k < M; ++k) {
+            const double dx = R[3 * j] - R[3 * k], dy = R[3 * j + 1] - R[3 * k + 1], dz = R[3 * j + 2] - R[3 * k + 2];
+            e += Z[j] * Z[k] / std::sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    c->Enuc = e;
+    c->has_nuclei = true;
+    return OFKS_OK;
+}
+
+int ofks_assemble(ofks_ctx *c) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_mesh) return fail(c, OFKS_ESTATE, "assemble: no mesh");
+    if (!c->has_nuclei) return fail(c, OFKS_ESTATE, "assemble: no nuclei (call ofks_nuclei_set, M may be 0)");
+    hipStream_t s = c->stream;
+    const int64_t nn = c->n_nodes, nt = c->n_tets;
+    free_system(c);
+    dfree(c, c->dof);
+    dfree(c, c->iptr);
+    dfree(c, c->inc);
+    dfree(c, c->geom);
+    dfree(c, c->vext_q);
+    int32_t *flags = nullptr, *errd = nullptr, *cursor = nullptr;
+    int64_t *scan = nullptr, *bsum = nullptr;
+    CHK(dalloc(c, &flags, nn + 1));
+    CHK(dalloc(c, &scan, nn + 1));
+    CHK(dalloc(c, &bsum, nn / 1024 + 2));
+    CHK(dalloc(c, &errd, 1));
+    CHK(dalloc(c, &cursor, nn));
+    CHK(dalloc(c, &c->dof, nn));
+    HIPCHK(hipMemsetAsync(errd, 0, sizeof(int32_t), s));
+    {
+        Scope sc(c, "assemble");
+        // interior DOF numbering in node order
+        HIPCHK(launch_interior_flags(s, nn, c->dir, flags));
+        HIPCHK(scan_exclusive(s, nn, flags, scan, bsum));
+        HIPCHK(launch_dof(s, nn, c->dir, scan, c->dof));
+    }
+    int64_t n = 0;
+    HIPCHK(hipMemcpyAsync(&n, scan + nn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (n <= 0) return fail(c, OFKS_EINVAL, "assemble: no interior nodes");
+    // node -> tetrahedra incidence
+    CHK(dalloc(c, &c->iptr, nn + 1));
+    CHK(dalloc(c, &c->inc, 4 * nt));
+    HIPCHK(hipMemsetAsync(flags, 0, (nn + 1) * sizeof(int32_t), s));
+    HIPCHK(hipMemsetAsync(cursor, 0, nn * sizeof(int32_t), s));
+    {
+        Scope sc(c, "assemble");
+        HIPCHK(launch_inc_count(s, nt, c->tets, flags));
+        HIPCHK(scan_exclusive(s, nn, flags, c->iptr, bsum));
+        HIPCHK(launch_inc_fill(s, nt, c->tets, c->iptr, cursor, c->inc));
+        HIPCHK(launch_inc_sort(s, nn, c->iptr, c->inc, errd));
+    }
+    // CSR pattern
+    CHK(dalloc(c, &c->rp, n + 1));
+    int32_t *rowcnt = nullptr;
+    CHK(dalloc(c, &rowcnt, n + 1));
+    {
+        Scope sc(c, "assemble");
+        HIPCHK(launch_row_pattern(s, nn, 0, c->dof, c->iptr, c->inc, c->tets, rowcnt, nullptr, nullptr, errd));
+        HIPCHK(scan_exclusive(s, n, rowcnt, c->rp, bsum));
+    }
+    int64_t nnz = 0;
+    int32_t errh = 0;
+    HIPCHK(hipMemcpyAsync(&nnz, c->rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&errh, errd, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (errh & 1) return fail(c, OFKS_ECAPACITY, "assemble: a node touches more than 128 tetrahedra");
+    if (errh & 2) return fail(c, OFKS_ECAPACITY, "assemble: a matrix row has more than 64 entries");
+    if (nnz >= (int64_t(1) << 31)) return fail(c, OFKS_ECAPACITY, "assemble: nnz exceeds 2^31");
+    CHK(dalloc(c, &c->col, nnz));
+    CHK(dalloc(c, &c->Lv, nnz));
+    CHK(dalloc(c, &c->Bv, nnz));
+    CHK(dalloc(c, &c->Mv, nnz));
+    CHK(dalloc(c, &c->hb, nnz));
+    CHK(dalloc(c, &c->lb, nnz));
+    CHK(dalloc(c, &c->geom, 13 * nt));
+    CHK(dalloc(c, &c->vext_q, 4 * nt));
+    c->n = n;
+    c->nnz = nnz;
+    CHK(alloc_system_common(c));
+    {
+        Scope sc(c, "assemble");
+        HIPCHK(launch_row_pattern(s, nn, 1, c->dof, c->iptr, c->inc, c->tets, nullptr, c->rp, c->col, errd));
+        HIPCHK(launch_tet_geom(s, nt, c->xyz, c->tets, c->geom, errd));
+        HIPCHK(launch_vext(s, nt, c->xyz, c->tets, c->M, c->Zd, c->Rd, c->vext_q));
+        HIPCHK(launch_assemble(s, nn, 0, c->dof, c->iptr, c->inc, c->tets, c->geom, c->vext_q, c->rp, c->col, c->Lv,
+                               c->Bv, c->Mv, c->hb, c->lb, c->lhd, c->bd, c->hd));
+    }
+    HIPCHK(hipMemcpyAsync(&errh, errd, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (errh & 4) return fail(c, OFKS_EINVAL, "assemble: degenerate tetrahedron");
+    dfree(c, flags);
+    dfree(c, scan);
+    dfree(c, bsum);
+    dfree(c, errd);
+    dfree(c, cursor);
+    dfree(c, rowcnt);
+    // SCF work arrays
+    dfree(c, c->rho_q);
+    dfree(c, c->eps_q);
+    dfree(c, c->vxc_q);
+    dfree(c, c->veff_q);
+    dfree(c, c->bvec);
+    dfree(c, c->U);
+    dfree(c, c->cg_r);
+    dfree(c, c->cg_d);
+    dfree(c, c->cg_q);
+    dfree(c, c->cg_sc);
+    CHK(dalloc(c, &c->rho_q, 4 * nt));
+    CHK(dalloc(c, &c->eps_q, 4 * nt));
+    CHK(dalloc(c, &c->vxc_q, 4 * nt));
+    CHK(dalloc(c, &c->veff_q, 4 * nt));
+    CHK(dalloc(c, &c->bvec, n));
+    CHK(dalloc(c, &c->U, n));
+    CHK(dalloc(c, &c->cg_r, n));
+    CHK(dalloc(c, &c->cg_d, n));
+    CHK(dalloc(c, &c->cg_q, n));
+    CHK(dalloc(c, &c->cg_sc, 8));
+    HIPCHK(hipMemsetAsync(c->U, 0, n * sizeof(double), s));
+    c->has_system = true;
+    c->assembled = true;
+    c->has_lhalf = true;
+    c->has_x = false;
+    return sync(c);
+}
+
+int ofks_csr_info(ofks_ctx *c, int64_t *n, int64_t *nnz) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "no system");
+    if (n) *n = c->n;
+    if (nnz) *nnz = c->nnz;
+    return OFKS_OK;
+}
+
+int ofks_csr_get(ofks_ctx *c, int64_t *row_ptr, int32_t *col, double *L, double *B, double *H) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "no system");
+    hipStream_t s = c->stream;
+    if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, c->rp, (c->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (col) HIPCHK(hipMemcpyAsync(col, c->col, c->nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    double *tx = nullptr, *ty = nullptr;
+    if (L || B || H) {
+        CHK(dalloc(c, &tx, c->nnz));
+        CHK(dalloc(c, &ty, c->nnz));
+    }
+    if (L) {
+        if (!c->Lv) return fail(c, OFKS_ESTATE, "csr_get: no stiffness matrix for a loaded system");
+        HIPCHK(hipMemcpyAsync(L, c->Lv, c->nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (B || H) {
+        HIPCHK(launch_split_pairs(s, c->nnz, c->hb, tx, ty));
+        if (H) HIPCHK(hipMemcpyAsync(H, tx, c->nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (B) HIPCHK(hipMemcpyAsync(B, ty, c->nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(c, tx);
+    dfree(c, ty);
+    return OFKS_OK;
+}
+
+int ofks_csr_load(ofks_ctx *c, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                  const double *H, const double *B, const double *Lhalf) {
+    if (!c) return OFKS_EINVAL;
+    if (n <= 0 || nnz <= 0 || !row_ptr || !col || !H || !B) return fail(c, OFKS_EINVAL, "csr_load: bad arguments");
+    free_system(c);
+    hipStream_t s = c->stream;
+    c->n = n;
+    c->nnz = nnz;
+    CHK(dalloc(c, &c->rp, n + 1));
+    CHK(dalloc(c, &c->col, nnz));
+    CHK(dalloc(c, &c->hb, nnz));
+    CHK(dalloc(c, &c->lb, nnz));
+    CHK(alloc_system_common(c));
+    HIPCHK(hipMemcpyAsync(c->rp, row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->col, col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_make_pairs(s, nnz, H, B, c->hb));
+    int32_t *errd = nullptr;
+    CHK(dalloc(c, &errd, 1));
+    HIPCHK(hipMemsetAsync(errd, 0, sizeof(int32_t), s));
+    if (Lhalf) {
+        HIPCHK(launch_make_pairs(s, nnz, Lhalf, B, c->lb));
+        HIPCHK(launch_diag(s, n, c->rp, c->col, c->lb, c->lhd, c->bd, errd));
+        c->has_lhalf = true;
+    } else {
+        HIPCHK(launch_make_pairs(s, nnz, B, B, c->lb));
+        HIPCHK(launch_diag(s, n, c->rp, c->col, c->lb, nullptr, c->bd, errd));
+        c->has_lhalf = false;
+    }
+    HIPCHK(launch_diag(s, n, c->rp, c->col, c->hb, c->hd, nullptr, errd));
+    int32_t errh = 0;
+    HIPCHK(hipMemcpyAsync(&errh, errd, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(c, errd);
+    if (errh) return fail(c, OFKS_EINVAL, "csr_load: a row has no diagonal entry");
+    c->has_system = true;
+    c->assembled = false;
+    c->has_x = false;
+    return OFKS_OK;
+}
+
+int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
+    if (!c || !prm) return OFKS_EINVAL;
+    if (!(prm->beta >= 0.0) || !(prm->tol > 0.0) || prm->max_iter < 0 || prm->pcg_iters < 0 ||
+        prm->precond < 0 || prm->precond > 2 || prm->step_rule < 0 || prm->step_rule > 4 ||
+        (prm->precision != OFKS_F64 && prm->precision != OFKS_F32))
+        return fail(c, OFKS_EINVAL, "set_params: invalid parameter");
+    if (prm->precond == OFKS_PRECOND_PAPER && prm->pcg_iters < 1)
+        return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs pcg_iters >= 1");
+    if (prm->scf && !c->assembled) return fail(c, OFKS_ESTATE, "set_params: SCF needs an assembled mesh");
+    if (prm->precond == OFKS_PRECOND_PAPER && c->has_system && !c->has_lhalf)
+        return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs L/2 (csr_load without Lhalf)");
+    if (prm->precond == OFKS_PRECOND_LEARNED) return fail(c, OFKS_EINVAL, "set_params: learned form not built");
+    c->prm = *prm;
+    if (c->prm.energy_every < 1) c->prm.energy_every = 1;
+    c->has_params = true;
+    return OFKS_OK;
+}
+
+int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "set_x0: no system");
+    if (!c->has_params) return fail(c, OFKS_ESTATE, "set_x0: call ofks_set_params first");
+    if (p <= 0 || p > 1024 || !X0) return fail(c, OFKS_EINVAL, "set_x0: need 1 <= p <= 1024 and a block");
+    if (p > c->n) return fail(c, OFKS_EINVAL, "set_x0: p exceeds n");
+    free_blocks<double>(c);
+    free_blocks<float>(c);
+    dfree(c, c->active);
+    dfree(c, c->rz);
+    c->p = p;
+    c->prec = c->prm.precision;
+    CHK(dalloc(c, &c->active, p));
+    CHK(dalloc(c, &c->rz, p));
+    CHK(alloc_blocks<double>(c));
+    Blocks<double> &B = c->b64;
+    HIPCHK(hipMemcpyAsync(B.Xt, X0, (size_t)c->n * p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (orth) {
+        // Cholesky-based Gram-Schmidt: V^T B V = R^T R, X0 = V R^-1
+        HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, B.Xt, B.BX, nullptr, 1));
+        std::vector<double> St, Lt;
+        CHK(gram<double>(c, B.Xt, B.BX, B.BX, St, Lt));
+        for (int a = 0; a < p; ++a)
+            for (int b = a + 1; b < p; ++b) St[a * p + b] = St[b * p + a] = 0.5 * (St[a * p + b] + St[b * p + a]);
+        if (!dense::cholesky(St, p)) return fail(c, OFKS_ENOTSPD, "set_x0: V^T B V is not positive definite");
+        std::vector<double> Li = dense::lower_inverse(St, p);
+        std::vector<double> Rinv((size_t)p * p);  // R^-1 = (L^-1)^T, upper triangular
+        for (int a = 0; a < p; ++a)
+            for (int b = 0; b < p; ++b) Rinv[a * p + b] = Li[b * p + a];
+        std::vector<double> ones(p, 1.0);
+        CHK(upload<double>(c, B.dinv, ones));
+        CHK(upload<double>(c, B.CC, Rinv));
+        GradArgs ga{};
+        HIPCHK(launch_rowgemm<double>(c->stream, EPI_PLAIN, c->n, p, p, c->gemm_rows, B.Xt, B.dinv, B.CC, B.HX, ga,
+                                      nullptr));
+        std::swap(B.Xt, B.HX);
+    }
+    if (c->prec == OFKS_F32) {
+        if (!c->hb32) CHK(ensure_f32_matrices(c));
+        else CHK(ensure_f32_matrices(c));
+        CHK(alloc_blocks<float>(c));
+        HIPCHK(launch_convert<double, float>(c->stream, c->n * (int64_t)p, B.Xt, c->b32.Xt));
+        CHK(sync(c));
+        free_blocks<double>(c);
+    }
+    c->dinv_h.assign(p, 1.0);
+    c->k = 0;
+    c->kkt0 = -1.0;
+    c->eta = 0.0;
+    c->eta0 = 0.0;
+    c->have_prev = false;
+    c->done = false;
+    c->has_x = true;
+    c->ehist.clear();
+    return sync(c);
+}
+
+int ofks_step(ofks_ctx *c, int32_t max_steps, ofks_iter_stats *stats, int32_t *n_stats, int32_t *done) {
+    CHK(check_ready(c));
+    int ns = 0;
+    int rc = OFKS_OK;
+    for (int s = 0; s < max_steps && !c->done; ++s) {
+        bool stop = false;
+        ofks_iter_stats st{};
+        if (c->prec == OFKS_F64) rc = iterate<double>(c, &st, &stop);
+        else rc = iterate<float>(c, &st, &stop);
+        if (rc < 0) break;
+        if (stats) stats[ns] = st;
+        ++ns;
+        if (stop) {
+            c->done = true;
+            break;
+        }
+        if (c->prec == OFKS_F32 && c->prm.refine_tol > 0.0 && st.rel < c->prm.refine_tol) {
+            rc = promote_to_f64(c);
+            if (rc < 0) break;
+        }
+    }
+    if (n_stats) *n_stats = ns;
+    if (done) *done = c->done ? 1 : 0;
+    if (rc < 0) return rc;
+    if (c->done && !(c->last_rel < c->prm.tol)) return OFKS_NOT_CONVERGED;
+    return OFKS_OK;
+}
+
+int ofks_residual(ofks_ctx *c, double *kkt, double *fea, double *rel) {
+    CHK(check_ready(c));
+    if (std::isnan(c->last_rel)) {
+        return fail(c, OFKS_ESTATE, "residual: no iteration evaluated yet (call ofks_step)");
+    }
+    if (kkt) *kkt = c->last_kkt;
+    if (fea) *fea = c->last_fea;
+    if (rel) *rel = c->last_rel;
+    return OFKS_OK;
+}
+
+int ofks_energy(ofks_ctx *c, double *parts) {
+    CHK(check_ready(c));
+    if (!parts) return fail(c, OFKS_EINVAL, "energy: null output");
+    for (int i = 0; i < 8; ++i) parts[i] = NAN;
+    if (c->S.empty()) return fail(c, OFKS_ESTATE, "energy: no iteration evaluated yet");
+    const int p = c->p;
+    double trl = 0.0;
+    for (int i = 0; i < p; ++i) trl += c->L0[i * p + i];
+    if (c->prm.scf) {
+        const double f = c->prm.occupation;
+        const double har = c->scf_parts[3], xc = c->scf_parts[1], vrho = c->scf_parts[2];
+        // f tr(X^T H X) = one-electron + int (V_H + v_xc) rho, int V_H rho = 2 E_H
+        parts[0] = f * trl - 2.0 * har - vrho;
+        parts[1] = har;
+        parts[2] = xc;
+        parts[3] = c->Enuc;
+        parts[4] = parts[0] + har + xc + c->Enuc;
+        parts[5] = c->scf_parts[0];
+        parts[6] = f * trl;
+        parts[7] = vrho;
+    } else {
+        double tr;
+        if (!dense::trace_sinv_a(c->S, c->L0, p, tr)) return fail(c, OFKS_ENOTSPD, "energy: S not SPD");
+        parts[4] = tr;
+        parts[6] = trl;
+    }
+    return OFKS_OK;
+}
+
+int ofks_get_x(ofks_ctx *c, double *dev_X) {
+    CHK(check_ready(c));
+    if (!dev_X) return fail(c, OFKS_EINVAL, "get_x: null output");
+    if (c->prec == OFKS_F64) {
+        CHK(upload<double>(c, c->b64.dinv, c->dinv_h));
+        HIPCHK(launch_scale_copy<double, double>(c->stream, c->n, c->p, c->b64.Xt, c->b64.dinv, dev_X));
+    } else {
+        CHK(upload<float>(c, c->b32.dinv, c->dinv_h));
+        HIPCHK(launch_scale_copy<float, double>(c->stream, c->n, c->p, c->b32.Xt, c->b32.dinv, dev_X));
+    }
+    return sync(c);
+}
+
+int ofks_postprocess(ofks_ctx *c, double *eigs) {
+    CHK(check_ready(c));
+    if (c->prec != OFKS_F64) CHK(promote_to_f64(c));
+    Blocks<double> &B = c->b64;
+    const int p = c->p;
+    // normalized current iterate into Xt
+    CHK(upload<double>(c, B.dinv, c->dinv_h));
+    HIPCHK(launch_scale_copy<double, double>(c->stream, c->n, p, B.Xt, B.dinv, B.R));
+    std::swap(B.Xt, B.R);
+    std::vector<double> ones(p, 1.0);
+    c->dinv_h = ones;
+    CHK(upload<double>(c, B.dinv, ones));
+    if (c->prm.scf) CHK(build_h<double>(c, B.Xt, B.dinv));
+    HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, B.Xt, B.HX, B.BX, 0));
+    std::vector<double> St, Lt;
+    CHK(gram<double>(c, B.Xt, B.BX, B.HX, St, Lt));
+    std::vector<double> S(p * p), L0(p * p);
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            S[a * p + b] = 0.5 * (St[a * p + b] + St[b * p + a]);
+            L0[a * p + b] = 0.5 * (Lt[a * p + b] + Lt[b * p + a]);
+        }
+    std::vector<double> w, Y;
+    if (!dense::sym_gen_eig(L0, S, p, w, Y)) return fail(c, OFKS_ENOTSPD, "postprocess: X^T B X not SPD");
+    CHK(upload<double>(c, B.CC, Y));
+    GradArgs ga{};
+    HIPCHK(launch_rowgemm<double>(c->stream, EPI_PLAIN, c->n, p, p, c->gemm_rows, B.Xt, B.dinv, B.CC, B.R, ga,
+                                  nullptr));
+    std::swap(B.Xt, B.R);
+    // the rotated block starts a fresh BB history
+    c->have_prev = false;
+    c->eta = 0.0;
+    if (eigs)
+        for (int i = 0; i < p; ++i) eigs[i] = w[i];
+    return sync(c);
+}
+
+int ofks_get_density(ofks_ctx *c, double *dev_rho) {
+    CHK(check_ready(c));
+    if (!c->assembled) return fail(c, OFKS_ESTATE, "get_density: needs an assembled mesh");
+    if (!dev_rho) return fail(c, OFKS_EINVAL, "get_density: null output");
+    HIPCHK(hipMemcpyAsync(dev_rho, c->rho_q, 4 * c->n_tets * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return sync(c);
+}
+
+// ---- single kernels ----------------------------------------------------------
+
+int ofks_spmm(ofks_ctx *c, int32_t p, const double *X, double *HX, double *BX) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "spmm: no system");
+    if (p <= 0 || !X || !HX || !BX) return fail(c, OFKS_EINVAL, "spmm: bad arguments");
+    HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, X, HX, BX, 0));
+    return sync(c);
+}
+
+int ofks_gram(ofks_ctx *c, int32_t p, const double *X, const double *HX, const double *BX, double *S, double *L0) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "gram: no system");
+    if (p <= 0 || !X || !HX || !BX || !S || !L0) return fail(c, OFKS_EINVAL, "gram: bad arguments");
+    const int keep = c->p;
+    c->p = p;
+    std::vector<double> St, Lt;
+    int rc = gram<double>(c, X, BX, HX, St, Lt);
+    c->p = keep;
+    CHK(rc);
+    std::memcpy(S, St.data(), sizeof(double) * p * p);
+    std::memcpy(L0, Lt.data(), sizeof(double) * p * p);
+    return OFKS_OK;
+}
+
+int ofks_precondition(ofks_ctx *c, int32_t p, const double *lam, const double *G, double *P) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "precondition: needs L/2 and B");
+    if (p <= 0 || !lam || !G || !P) return fail(c, OFKS_EINVAL, "precondition: bad arguments");
+    const int m = c->prm.pcg_iters;
+    if (m < 1) return fail(c, OFKS_EINVAL, "precondition: pcg_iters must be >= 1");
+    const int64_t n = c->n;
+    const size_t np = (size_t)n * p;
+    double *R = nullptr, *D = nullptr, *Q = nullptr, *lamd = nullptr, *alpha = nullptr, *betad = nullptr,
+           *rzd = nullptr;
+    uint8_t *act = nullptr;
+    CHK(dalloc(c, &R, np));
+    CHK(dalloc(c, &D, np));
+    CHK(dalloc(c, &Q, np));
+    CHK(dalloc(c, &lamd, p));
+    CHK(dalloc(c, &alpha, p));
+    CHK(dalloc(c, &betad, p));
+    CHK(dalloc(c, &rzd, p));
+    CHK(dalloc(c, &act, p));
+    std::vector<double> lv(lam, lam + p);
+    std::vector<uint8_t> ah(p);
+    for (int i = 0; i < p; ++i) ah[i] = lam[i] < 0.0 ? 1 : 0;
+    CHK(upload<double>(c, lamd, lv));
+    CHK(upload_bytes(c, act, ah.data(), p));
+    CHK(ensure_part(c, (size_t)c->grid * p));
+    HIPCHK(launch_pcg_init<double>(c->stream, c->grid, n, p, act, c->lhd, c->bd, lamd, G, R, D, P, c->part));
+    HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, rzd));
+    for (int it = 0; it < m; ++it) {
+        HIPCHK(launch_spmm_shift<double>(c->stream, c->grid, n, p, c->rp, c->col, c->lb, lamd, act, D, Q, c->part));
+        HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+        HIPCHK(launch_pcg_scalars<double>(c->stream, p, 0, c->red, rzd, alpha));
+        HIPCHK(launch_pcg_xr<double>(c->stream, c->grid, n, p, it == 0, alpha, act, c->lhd, c->bd, lamd, D, Q, P, R,
+                                     c->part));
+        HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+        if (it + 1 < m) {
+            HIPCHK(launch_pcg_scalars<double>(c->stream, p, 1, c->red, rzd, betad));
+            HIPCHK(launch_pcg_dir<double>(c->stream, n, p, betad, act, c->lhd, c->bd, lamd, R, D));
+        }
+    }
+    CHK(sync(c));
+    dfree(c, R);
+    dfree(c, D);
+    dfree(c, Q);
+    dfree(c, lamd);
+    dfree(c, alpha);
+    dfree(c, betad);
+    dfree(c, rzd);
+    dfree(c, act);
+    return OFKS_OK;
+}
+
+int ofks_build_hamiltonian(ofks_ctx *c, int32_t p, const double *X, double *rho_q, double *eps_q, double *vxc_q,
+                           double *U, double *parts) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->assembled) return fail(c, OFKS_ESTATE, "build_hamiltonian: needs an assembled mesh");
+    if (p <= 0 || !X) return fail(c, OFKS_EINVAL, "build_hamiltonian: bad arguments");
+    if (!c->has_params) ofks_default_params(&c->prm);
+    double *ones = nullptr;
+    CHK(dalloc(c, &ones, p));
+    std::vector<double> o(p, 1.0);
+    CHK(upload<double>(c, ones, o));
+    const int keep = c->p;
+    c->p = p;
+    int rc = build_h<double>(c, X, ones);
+    c->p = keep;
+    dfree(c, ones);
+    CHK(rc);
+    hipStream_t s = c->stream;
+    const size_t bq = 4 * c->n_tets * sizeof(double);
+    if (rho_q) HIPCHK(hipMemcpyAsync(rho_q, c->rho_q, bq, hipMemcpyDeviceToDevice, s));
+    if (eps_q) HIPCHK(hipMemcpyAsync(eps_q, c->eps_q, bq, hipMemcpyDeviceToDevice, s));
+    if (vxc_q) HIPCHK(hipMemcpyAsync(vxc_q, c->vxc_q, bq, hipMemcpyDeviceToDevice, s));
+    if (U) HIPCHK(hipMemcpyAsync(U, c->U, c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (parts)
+        for (int i = 0; i < 4; ++i) parts[i] = c->scf_parts[i];
+    return sync(c);
+}
+
+int ofks_timing(ofks_ctx *c, int32_t enable) {
+    if (!c) return OFKS_EINVAL;
+    CHK(sync(c));
+    c->timing = enable != 0;
+    c->timers.clear();
+    return OFKS_OK;
+}
+
+int ofks_timer_get(ofks_ctx *c, const char *name, double *ms, int64_t *launches) {
+    if (!c || !name) return OFKS_EINVAL;
+    CHK(sync(c));
+    auto it = c->timers.find(name);
+    if (ms) *ms = it == c->timers.end() ? 0.0 : it->second.ms;
+    if (launches) *launches = it == c->timers.end() ? 0 : it->second.launches;
+    return OFKS_OK;
+}
+
+}  // extern "C"

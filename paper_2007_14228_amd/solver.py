@@ -1,0 +1,263 @@
+"""Python binding of the ofks C ABI: argument marshalling only.
+
+Every computation runs in libofks.so.  Device buffers are torch tensors on
+the current HIP device; the solver is bound to the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import IterStats, Params
+
+
+class OfksError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ofks error {code}: {msg}")
+        self.code = code
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check_block(X, n: int):
+    if X.dim() != 2 or int(X.shape[0]) != n or int(X.shape[1]) < 1:
+        raise ValueError(f"expected an n x p block with n = {n}, got {tuple(X.shape)}")
+
+
+def _dev_ptr(t, dtype_name: str = "float64"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (HIP) torch tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"expected torch.{dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One ofks context on the current torch HIP stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.lib = _lib.load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = ctypes.c_void_p()
+        self._check(self.lib.ofks_create(ctypes.byref(h), ctypes.c_void_p(stream.cuda_stream)), ctx=None)
+        self.h = h
+        self.p = 0
+        self.n = 0
+        self.n_tets = 0
+        self.params = self.default_params()
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, rc: int, ctx="self"):
+        if rc < 0 or (rc > 0 and rc != _lib.OFKS_NOT_CONVERGED):
+            msg = ""
+            if ctx is not None and getattr(self, "h", None) is not None:
+                msg = self.lib.ofks_last_error(self.h).decode()
+            raise OfksError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.ofks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def default_params(self) -> Params:
+        p = Params()
+        self.lib.ofks_default_params(ctypes.byref(p))
+        return p
+
+    # -- discretization ----------------------------------------------------
+    def mesh_load(self, xyz: np.ndarray, tets: np.ndarray, dirichlet: np.ndarray):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        dirichlet = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        self._check(self.lib.ofks_mesh_load(self.h, xyz.shape[0], _np_ptr(xyz), tets.shape[0], _np_ptr(tets),
+                                            _np_ptr(dirichlet)))
+        self.n_tets = int(tets.shape[0])
+
+    def nuclei_set(self, Z: np.ndarray, R: np.ndarray):
+        Z = np.ascontiguousarray(Z, dtype=np.float64)
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
+        self._check(self.lib.ofks_nuclei_set(self.h, int(Z.shape[0]), _np_ptr(Z), _np_ptr(R)))
+
+    def assemble(self):
+        self._check(self.lib.ofks_assemble(self.h))
+        self.n, self.nnz = self.csr_info()
+
+    def load_workload(self, w):
+        """Mesh + nuclei + device assembly for a workloads.Workload."""
+        self.mesh_load(w.mesh.xyz, w.mesh.tets, w.mesh.dirichlet)
+        self.nuclei_set(w.Z, w.R)
+        self.assemble()
+
+    def csr_info(self) -> Tuple[int, int]:
+        n = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        self._check(self.lib.ofks_csr_info(self.h, ctypes.byref(n), ctypes.byref(nnz)))
+        return int(n.value), int(nnz.value)
+
+    def csr_get(self, values: bool = True) -> Dict[str, np.ndarray]:
+        n, nnz = self.csr_info()
+        rp = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(nnz, dtype=np.int32)
+        out = dict(row_ptr=rp, col=col)
+        L = B = H = None
+        if values:
+            L = np.empty(nnz)
+            B = np.empty(nnz)
+            H = np.empty(nnz)
+            out.update(L=L, B=B, H=H)
+        nul = ctypes.c_void_p(None)
+        self._check(self.lib.ofks_csr_get(self.h, _np_ptr(rp), _np_ptr(col),
+                                          _np_ptr(L) if L is not None else nul,
+                                          _np_ptr(B) if B is not None else nul,
+                                          _np_ptr(H) if H is not None else nul))
+        return out
+
+    def csr_load(self, row_ptr, col, H, B, Lhalf=None):
+        n = int(row_ptr.shape[0] - 1)
+        nnz = int(col.shape[0])
+        rp_h = row_ptr.cpu().numpy()
+        col_h = col.cpu().numpy()
+        if rp_h[0] != 0 or rp_h[-1] != nnz or np.any(np.diff(rp_h) < 0):
+            raise ValueError("row_ptr is not a valid CSR offset array")
+        if nnz and (col_h.min() < 0 or col_h.max() >= n):
+            raise ValueError("column index out of range")
+        for v in (H, B) + ((Lhalf,) if Lhalf is not None else ()):
+            if int(v.shape[0]) != nnz:
+                raise ValueError("value arrays must have nnz entries")
+        self._check(self.lib.ofks_csr_load(self.h, n, nnz, _dev_ptr(row_ptr, "int64"), _dev_ptr(col, "int32"),
+                                           _dev_ptr(H), _dev_ptr(B),
+                                           _dev_ptr(Lhalf) if Lhalf is not None else ctypes.c_void_p(None)))
+        self.n, self.nnz = n, nnz
+
+    # -- setup ---------------------------------------------------------------
+    def set_params(self, **kw):
+        p = self.default_params()
+        for k, v in kw.items():
+            if k == "precond" and isinstance(v, str):
+                v = _lib.PRECOND[v]
+            elif k == "step_rule" and isinstance(v, str):
+                v = _lib.STEP[v]
+            elif k == "precision" and isinstance(v, str):
+                v = _lib.PRECISION[v]
+            elif k == "precond_lambda" and isinstance(v, str):
+                v = {"lambda2": 0, "lambda0": 1}[v]
+            if not hasattr(p, k):
+                raise KeyError(k)
+            setattr(p, k, v)
+        self._check(self.lib.ofks_set_params(self.h, ctypes.byref(p)))
+        self.params = p
+
+    def set_x0(self, X0, orthonormalize: bool = True):
+        _check_block(X0, self.n)
+        p = int(X0.shape[1])
+        self._check(self.lib.ofks_set_x0(self.h, p, _dev_ptr(X0), 1 if orthonormalize else 0))
+        self.p = p
+
+    # -- iteration -----------------------------------------------------------
+    def step(self, max_steps: int = 1) -> Tuple[List[dict], bool, int]:
+        buf = (IterStats * max(1, max_steps))()
+        ns = ctypes.c_int32()
+        done = ctypes.c_int32()
+        rc = self._check(self.lib.ofks_step(self.h, max_steps, buf, ctypes.byref(ns), ctypes.byref(done)))
+        out = []
+        for i in range(ns.value):
+            s = buf[i]
+            out.append({f: getattr(s, f) for f, _ in IterStats._fields_})
+        return out, bool(done.value), rc
+
+    def residual(self) -> Tuple[float, float, float]:
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.ofks_residual(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def energy(self) -> np.ndarray:
+        parts = np.empty(8)
+        self._check(self.lib.ofks_energy(self.h, _np_ptr(parts)))
+        return parts
+
+    def postprocess(self) -> np.ndarray:
+        eig = np.empty(self.p)
+        self._check(self.lib.ofks_postprocess(self.h, _np_ptr(eig)))
+        return eig
+
+    def get_x(self):
+        import torch
+        X = torch.empty((self.n, self.p), dtype=torch.float64, device="cuda")
+        self._check(self.lib.ofks_get_x(self.h, _dev_ptr(X)))
+        return X
+
+    def get_density(self):
+        import torch
+        rho = torch.empty((self.n_tets, 4), dtype=torch.float64, device="cuda")
+        self._check(self.lib.ofks_get_density(self.h, _dev_ptr(rho)))
+        return rho
+
+    # -- single kernels -------------------------------------------------------
+    def spmm(self, X):
+        import torch
+        _check_block(X, self.n)
+        HX = torch.empty_like(X)
+        BX = torch.empty_like(X)
+        self._check(self.lib.ofks_spmm(self.h, int(X.shape[1]), _dev_ptr(X), _dev_ptr(HX), _dev_ptr(BX)))
+        return HX, BX
+
+    def gram(self, X, HX, BX):
+        for Y in (X, HX, BX):
+            _check_block(Y, self.n)
+        if not (X.shape == HX.shape == BX.shape):
+            raise ValueError("X, HX, BX must have the same shape")
+        p = int(X.shape[1])
+        S = np.empty((p, p))
+        L0 = np.empty((p, p))
+        self._check(self.lib.ofks_gram(self.h, p, _dev_ptr(X), _dev_ptr(HX), _dev_ptr(BX), _np_ptr(S),
+                                       _np_ptr(L0)))
+        return S, L0
+
+    def precondition(self, lam: np.ndarray, G):
+        import torch
+        _check_block(G, self.n)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (int(G.shape[1]),):
+            raise ValueError("lam must have one entry per column")
+        P = torch.empty_like(G)
+        self._check(self.lib.ofks_precondition(self.h, int(G.shape[1]), _np_ptr(lam), _dev_ptr(G), _dev_ptr(P)))
+        return P
+
+    def build_hamiltonian(self, X):
+        import torch
+        _check_block(X, self.n)
+        q = lambda: torch.empty((self.n_tets, 4), dtype=torch.float64, device="cuda")
+        rho, eps, vxc = q(), q(), q()
+        U = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        parts = np.empty(4)
+        self._check(self.lib.ofks_build_hamiltonian(self.h, int(X.shape[1]), _dev_ptr(X), _dev_ptr(rho),
+                                                    _dev_ptr(eps), _dev_ptr(vxc), _dev_ptr(U), _np_ptr(parts)))
+        return dict(rho=rho, eps=eps, vxc=vxc, U=U, parts=parts)
+
+    # -- timing ----------------------------------------------------------------
+    def timing(self, enable: bool = True):
+        self._check(self.lib.ofks_timing(self.h, 1 if enable else 0))
+
+    def timer(self, name: str) -> Tuple[float, int]:
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.ofks_timer_get(self.h, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, int(n.value)

@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: indexing bit-exact; FP64 single-kernel results 1e-12 relative
+(summation order differs); converged energies and eigenvalues 1e-10 relative.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import fem, native, pcal, scf
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _solver_for(w):
+    from paper_2007_14228_amd import Solver
+    s = Solver()
+    s.load_workload(w)
+    return s
+
+
+def _relerr(a, b):
+    scale = max(np.abs(b).max(), 1e-300)
+    return float(np.abs(a - b).max() / scale)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = wl.make_workload("c1")
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    return w, d
+
+
+@pytest.fixture(scope="module")
+def graded():
+    """A graded multi-nucleus mesh: rows of different lengths, several tiles."""
+    Z = np.array([6.0, 1.0, 8.0])
+    R = np.array([[0.3, -0.2, 0.1], [-1.4, 0.9, 0.4], [1.1, 1.3, -0.9]])
+    mesh = wl.graded_mesh(5.0, Z, R, gamma1=0.5, gamma2=1.2, hmin=0.1)
+    w = wl.Workload("graded", mesh, Z, R, p=7, beta=1.0, scf=False, seed=0)
+    return w, fem.discretize(mesh, Z, R)
+
+
+@pytest.mark.parametrize("which", ["c1", "graded"])
+def test_csr_pattern_bit_exact_and_values(which, c1, graded):
+    w, d = c1 if which == "c1" else graded
+    print(f"[gpu] csr parity {which} n={d.n} nnz={d.nnz}", flush=True)
+    s = _solver_for(w)
+    g = s.csr_get()
+    assert np.array_equal(g["row_ptr"], d.row_ptr)
+    assert np.array_equal(g["col"], d.col)
+    assert _relerr(g["L"], d.L) < 1e-13
+    assert _relerr(g["B"], d.B) < 1e-13
+    assert _relerr(g["H"], d.H) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 3, 4, 11, 16, 33, 64, 128, 130])
+def test_dual_spmm(p, graded):
+    w, d = graded
+    print(f"[gpu] spmm p={p}", flush=True)
+    s = _solver_for(w)
+    X = np.random.default_rng(p).standard_normal((d.n, p))
+    HX, BX = s.spmm(_dev(X))
+    assert _relerr(_host(HX), native.spmm(d.row_ptr, d.col, d.H, X)) < 1e-12
+    assert _relerr(_host(BX), native.spmm(d.row_ptr, d.col, d.B, X)) < 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 4, 11, 33, 128])
+def test_gram(p, graded):
+    w, d = graded
+    print(f"[gpu] gram p={p}", flush=True)
+    s = _solver_for(w)
+    rng = np.random.default_rng(100 + p)
+    X, HX, BX = (rng.standard_normal((d.n, p)) for _ in range(3))
+    S, L0 = s.gram(_dev(X), _dev(HX), _dev(BX))
+    assert _relerr(S, X.T @ BX) < 1e-12
+    assert _relerr(L0, X.T @ HX) < 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 5, 16])
+def test_preconditioner_cg(p, graded):
+    w, d = graded
+    print(f"[gpu] precondition p={p}", flush=True)
+    s = _solver_for(w)
+    s.set_params(precond="paper", pcg_iters=10)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    rng = np.random.default_rng(7 + p)
+    G = rng.standard_normal((d.n, p))
+    lam = -np.abs(rng.standard_normal(p)) - 0.1
+    if p > 1:
+        lam[1] = 0.5                        # identity branch
+    P = _host(s.precondition(lam, _dev(G)))
+    ref = pcal.precondition(prob, G, lam, pcal.Params(precond="paper", pcg_iters=10))
+    assert _relerr(P, ref) < 1e-11
+
+
+def _run_gpu(s, X0, max_iter, **params):
+    s.set_params(max_iter=max_iter, **params)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    stats, done, rc = s.step(max_iter + 1)
+    return stats
+
+
+@pytest.mark.parametrize("precond", ["none", "paper"])
+def test_first_iterations_follow_the_oracle(precond, c1):
+    """Step parity: kkt, fea, rel and eta of the first iterations from the same X0."""
+    w, d = c1
+    print(f"[gpu] step parity c1 {precond}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=6, precond=precond))
+    s = _solver_for(w)
+    st = _run_gpu(s, X0, 6, beta=w.beta, tol=1e-30, precond=precond, pcg_iters=10)
+    assert len(st) == len(hist) == 7
+    for a, b in zip(st, hist):
+        assert a["k"] == b.k
+        assert abs(a["kkt"] - b.kkt) <= 1e-10 * b.kkt
+        assert abs(a["fea"] - b.fea) <= 1e-10 * b.fea + 1e-13     # fea at k = 0 is rounding noise
+        assert abs(a["energy"] - b.energy) <= 1e-11 * abs(b.energy)
+    # eta used for each step (oracle records it at the next iterate)
+    for k in range(1, 7):
+        assert abs(st[k - 1]["eta"] - hist[k].eta) <= 1e-9 * hist[k].eta
+
+
+@pytest.mark.parametrize("precond", ["none", "paper"])
+def test_converged_eigenvalues_match_dense_lapack(precond, c1):
+    w, d = c1
+    print(f"[gpu] c1 converge {precond}", flush=True)
+    s = _solver_for(w)
+    X0 = wl.random_block(0, d.n, w.p)
+    s.set_params(beta=w.beta, tol=1e-10, max_iter=2000, precond=precond)
+    s.set_x0(_dev(X0), orthonormalize=True)
+    stats, done, rc = s.step(2000)
+    assert done and stats[-1]["rel"] < 1e-10
+    eig = s.postprocess()
+    ref = np.array(json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p])
+    assert np.allclose(eig, ref, rtol=1e-10, atol=0)
+    assert stats[-1]["fea"] < 1e-9
+
+
+def test_single_column_feasible_every_iterate(c1):
+    w, d = c1
+    print("[gpu] p=1", flush=True)
+    s = _solver_for(w)
+    s.set_params(beta=1.0, tol=1e-10, max_iter=1000, precond="paper")
+    s.set_x0(_dev(wl.random_block(5, d.n, 1)), orthonormalize=True)
+    stats, done, _ = s.step(1000)
+    assert done
+    assert max(x["fea"] for x in stats) < 1e-14
+    ref = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][0]
+    assert abs(stats[-1]["energy"] - ref) < 1e-10 * abs(ref)
+
+
+def test_get_x_is_b_orthonormal_at_convergence(c1):
+    w, d = c1
+    s = _solver_for(w)
+    s.set_params(beta=w.beta, tol=1e-10, max_iter=2000, precond="paper")
+    s.set_x0(_dev(wl.random_block(3, d.n, w.p)), orthonormalize=True)
+    s.step(2000)
+    X = _host(s.get_x())
+    S = X.T @ native.spmm(d.row_ptr, d.col, d.B, X)
+    assert np.abs(S - np.eye(w.p)).max() < 1e-9
+
+
+# ----------------------------------------------------------------------------
+# Kohn-Sham (SCF) pieces
+# ----------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def lih():
+    ax = wl.uniform_axis(-6.0, 6.0, 10)
+    mesh = wl.kuhn_mesh(ax, ax, ax)
+    Z = np.array([3.0, 1.0])
+    R = np.array([[-1.2, 0.0, 0.0], [1.2, 0.0, 0.0]])
+    w = wl.Workload("lih", mesh, Z, R, p=2, beta=1.0, scf=True, seed=0)
+    return w, fem.discretize(mesh, Z, R)
+
+
+def test_density_xc_hartree_and_hamiltonian(lih):
+    w, d = lih
+    print("[gpu] build_hamiltonian", flush=True)
+    prob = scf.KSProblem(d, w.Z, w.R)
+    X = pcal.chol_gs(prob, wl.random_block(2, d.n, 2))
+    s = _solver_for(w)
+    out = s.build_hamiltonian(_dev(X))
+    Hval, rho, U, parts = prob.build(X)
+    assert _relerr(_host(out["rho"]), rho) < 1e-13
+    from oracle.xc import lda_xc
+    eps, vxc = lda_xc(rho)
+    assert _relerr(_host(out["vxc"]), vxc) < 1e-12
+    assert _relerr(_host(out["eps"]), eps) < 1e-12
+    assert _relerr(_host(out["U"]), U) < 1e-10          # both CGs stop at 1e-12 relative residual
+    assert abs(out["parts"][0] - parts["nelec"]) < 1e-12 * parts["nelec"]
+    assert abs(out["parts"][1] - parts["xc"]) < 1e-12 * abs(parts["xc"])
+    assert abs(out["parts"][2] - parts["int_vxc_rho"]) < 1e-12 * abs(parts["int_vxc_rho"])
+    assert abs(out["parts"][3] - parts["har"]) < 1e-10 * parts["har"]
+    g = s.csr_get()
+    assert _relerr(g["H"], Hval) < 1e-11
+
+
+def test_scf_pcal_energy_matches_the_oracle(lih):
+    w, d = lih
+    print("[gpu] scf pcal", flush=True)
+    prob = scf.KSProblem(d, w.Z, w.R)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, 2))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=1.0, tol=1e-10, max_iter=2000, precond="paper"))
+    s = _solver_for(w)
+    s.set_params(beta=1.0, tol=1e-10, max_iter=2000, precond="paper", scf=1)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    stats, done, _ = s.step(2000)
+    assert done and stats[-1]["rel"] < 1e-10
+    E_ref = hist[-1].energy
+    assert abs(stats[-1]["energy"] - E_ref) < 1e-10 * abs(E_ref)
+    parts = s.energy()
+    assert abs(parts[4] - E_ref) < 1e-10 * abs(E_ref)
+    assert abs(parts[5] - 4.0) < 1e-9                     # 2 electrons per orbital, p = 2
+
+
+# ----------------------------------------------------------------------------
+# precision form
+# ----------------------------------------------------------------------------
+
+def test_mixed_precision_with_fp64_refinement(c1):
+    w, d = c1
+    print("[gpu] mixed c1", flush=True)
+    s = _solver_for(w)
+    s.set_params(beta=w.beta, tol=1e-10, max_iter=3000, precond="paper", precision="f32", refine_tol=1e-4)
+    s.set_x0(_dev(wl.random_block(0, d.n, w.p)), orthonormalize=True)
+    stats, done, _ = s.step(3000)
+    assert done
+    assert stats[0]["precision"] == 1 and stats[-1]["precision"] == 0
+    ref = np.array(json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p])
+    assert abs(stats[-1]["energy"] - ref.sum()) < 1e-6
+
+
+# ----------------------------------------------------------------------------
+# errors are reported, not faulted
+# ----------------------------------------------------------------------------
+
+def test_invalid_calls_return_errors(c1):
+    from paper_2007_14228_amd import OfksError, Solver
+    w, d = c1
+    s = Solver()
+    with pytest.raises(OfksError):
+        s.step(1)                                   # no system
+    s.load_workload(w)
+    with pytest.raises(OfksError):
+        s.set_params(precond="paper", pcg_iters=0)
+    s.set_params()
+    with pytest.raises(ValueError):
+        s.set_x0(_dev(np.zeros((d.n + 1, 2))))      # wrong row count, caught before the call
+    with pytest.raises(OfksError):
+        s.set_x0(_dev(np.zeros((d.n, 3))))          # V^T B V singular

@@ -108,7 +108,7 @@ def graded_axis(lo: float, hi: float, anchors: Sequence[float], zs: Sequence[flo
     consecutive anchors the cell count is ceil(int dx / h(x)) and nodes are
     placed at equal increments of int dx / h(x).
     """
-    a, z = _merge_anchors(anchors, zs, 0.5 * hmin)
+    a, z = _merge_anchors(anchors, zs, hmin)
     keep = (a > lo + hmin) & (a < hi - hmin)
     a, z = a[keep], z[keep]
     breaks = np.concatenate([[lo], a, [hi]])
