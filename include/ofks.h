@@ -195,8 +195,8 @@ int ofks_build_hamiltonian(ofks_ctx *ctx, int32_t p, const double *X, double *rh
  * recording and clears the totals. */
 int ofks_timing(ofks_ctx *ctx, int32_t enable);
 /* Totals for a kernel class: name is one of "spmm_dual", "spmm_shift",
- * "gram", "update_a", "update_b", "pcg_axpy", "density", "poisson", "assemble_h",
- * "bbdot", "mlp".  ms = summed duration, launches = count. */
+ * "gram", "update_a", "update_b", "pcg_xr", "pcg_dir", "density", "poisson",
+ * "assemble_h", "bbdot", "mlp".  ms = summed duration, launches = count. */
 int ofks_timer_get(ofks_ctx *ctx, const char *name, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

@@ -560,28 +560,46 @@ static inline int lpr_l2(int p, int v) {
     return l > 6 ? 6 : l;
 }
 
-template <typename T>
-hipError_t launch_gram(hipStream_t s, int64_t n, int p, int target_blocks, const T *X, const T *BX,
-                       const T *HX, double *part, int *nsplit_out) {
-    int mt, nt;
-    if (p <= 16) { mt = 1; nt = 2; }
-    else if (p <= 32) { mt = 2; nt = 4; }
-    else { mt = 4; nt = 4; }
-    const int tm = 16 * mt, tn = 16 * nt;
-    const int gx = (p + tm - 1) / tm, gy = (2 * p + tn - 1) / tn;
-    int64_t splits = target_blocks / (gx * gy);
+// Split-K plan of k_gram: output tiles (gx x gy) and row splits, so that the
+// caller can size the partial buffer (splits * p * 2p doubles) before launch.
+struct GramPlan {
+    int mt, nt, gx, gy;
+    int64_t splits, rows_per_split;
+};
+
+GramPlan gram_plan(int64_t n, int p, int target_blocks) {
+    GramPlan g{};
+    if (p <= 16) { g.mt = 1; g.nt = 2; }
+    else if (p <= 32) { g.mt = 2; g.nt = 4; }
+    else if (p <= 64) { g.mt = 4; g.nt = 4; }
+    else { g.mt = 8; g.nt = 8; }
+    const int tm = 16 * g.mt, tn = 16 * g.nt;
+    g.gx = (p + tm - 1) / tm;
+    g.gy = (2 * p + tn - 1) / tn;
+    int64_t splits = target_blocks / (g.gx * g.gy);
     if (splits < 1) splits = 1;
     int64_t rps = (n + splits - 1) / splits;
     rps = ((rps + 15) / 16) * 16;
     if (rps < 16) rps = 16;
     splits = (n + rps - 1) / rps;
     if (splits < 1) splits = 1;
-    *nsplit_out = (int)splits;
-    dim3 grid(gx, gy, (unsigned)splits);
+    g.splits = splits;
+    g.rows_per_split = rps;
+    return g;
+}
+
+template <typename T>
+hipError_t launch_gram(hipStream_t s, int64_t n, int p, const GramPlan &g, const T *X, const T *BX,
+                       const T *HX, double *part, size_t part_capacity) {
+    if ((size_t)g.splits * (size_t)p * 2 * p > part_capacity) return hipErrorInvalidValue;
+    if (g.splits > 65535) return hipErrorInvalidValue;
+    dim3 grid(g.gx, g.gy, (unsigned)g.splits);
     using ACC = T;
-    if (mt == 1) hipLaunchKernelGGL((k_gram<T, ACC, 1, 2>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
-    else if (mt == 2) hipLaunchKernelGGL((k_gram<T, ACC, 2, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
-    else hipLaunchKernelGGL((k_gram<T, ACC, 4, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    const int64_t rps = g.rows_per_split;
+    if (g.mt == 1) hipLaunchKernelGGL((k_gram<T, ACC, 1, 2>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    else if (g.mt == 2) hipLaunchKernelGGL((k_gram<T, ACC, 2, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    else if (g.mt == 4) hipLaunchKernelGGL((k_gram<T, ACC, 4, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    else hipLaunchKernelGGL((k_gram<T, ACC, 8, 8>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
     return hipGetLastError();
 }
 
@@ -591,13 +609,17 @@ hipError_t launch_colsum(hipStream_t s, int64_t nb, int64_t m, const double *par
     return hipGetLastError();
 }
 
+// Column tile width of k_rowgemm for N output columns (16 * NT).
+int rowgemm_tile_cols(int N) { return N <= 16 ? 16 : (N <= 32 ? 32 : 64); }
+
 // number of blocks along rows for k_rowgemm epilogues (fixed => deterministic)
 template <typename T>
 hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int grid_rows, const T *A,
                           const T *sa, const T *M, T *Y, GradArgs ga, int *gx_out) {
+    const int tc = rowgemm_tile_cols(N);
+    const int nt = tc / 16;
     const int mt = 4;
-    const int nt = (N <= 16) ? 1 : ((N <= 32) ? 2 : 4);
-    const int tr = 16 * mt, tc = 16 * nt;
+    const int tr = 16 * mt;
     const int64_t ntiles = (n + tr - 1) / tr;
     int gx = grid_rows;
     if (gx > ntiles) gx = (int)ntiles;
@@ -605,16 +627,16 @@ hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int g
     const int gy = (N + tc - 1) / tc;
     if (gx_out) *gx_out = gx;
     dim3 grid(gx, gy);
-#define OFKS_RG(NT_)                                                                          \
-    if (nt == NT_) {                                                                          \
-        if (epi == EPI_PLAIN) hipLaunchKernelGGL((k_rowgemm<T, 4, NT_, EPI_PLAIN>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
-        else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_rowgemm<T, 4, NT_, EPI_GRAD>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
-        else hipLaunchKernelGGL((k_rowgemm<T, 4, NT_, EPI_GRAD_PCG>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+#define OFKS_RG(MT_, NT_)                                                                     \
+    if (nt == NT_ && mt == MT_) {                                                             \
+        if (epi == EPI_PLAIN) hipLaunchKernelGGL((k_rowgemm<T, MT_, NT_, EPI_PLAIN>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_rowgemm<T, MT_, NT_, EPI_GRAD>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else hipLaunchKernelGGL((k_rowgemm<T, MT_, NT_, EPI_GRAD_PCG>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
         return hipGetLastError();                                                             \
     }
-    OFKS_RG(1)
-    OFKS_RG(2)
-    OFKS_RG(4)
+    OFKS_RG(4, 1)
+    OFKS_RG(4, 2)
+    OFKS_RG(4, 4)
 #undef OFKS_RG
     return hipErrorInvalidValue;
 }
@@ -730,7 +752,7 @@ template hipError_t launch_pcg_init<float>(hipStream_t, int, int64_t, int, const
                                            float *, double *);
 
 #define OFKS_INST(T)                                                                                  \
-    template hipError_t launch_gram<T>(hipStream_t, int64_t, int, int, const T *, const T *, const T *, double *, int *); \
+    template hipError_t launch_gram<T>(hipStream_t, int64_t, int, const GramPlan &, const T *, const T *, const T *, double *, size_t); \
     template hipError_t launch_rowgemm<T>(hipStream_t, int, int64_t, int, int, int, const T *, const T *, const T *, T *, GradArgs, int *); \
     template hipError_t launch_pcg_xr<T>(hipStream_t, int, int64_t, int, int, const T *, const uint8_t *, const double *, const double *, const T *, const T *, const T *, T *, T *, double *); \
     template hipError_t launch_coldot<T>(hipStream_t, int, int64_t, int, const T *, const T *, double *); \

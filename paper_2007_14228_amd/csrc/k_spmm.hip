@@ -1,22 +1,26 @@
 // Sparse products on the shared P1 CSR pattern.
 //
 //  k_spmm_pair   : Y1 = A1 X and Y2 = A2 X in one pass (H X and B X, the
-//                  "function evaluation" of Algorithm PCAL); values of the
-//                  two matrices are interleaved per nonzero so one 16-byte
-//                  (f64) or 8-byte (f32) load feeds both products.
-//  k_spmm_one    : Y = A X (B X alone: column norms, Cholesky-Gram-Schmidt).
+//                  "function evaluation" of Algorithm PCAL).  The values of the
+//                  two matrices are interleaved per nonzero, so one 16-byte
+//                  (f64) or 8-byte (f32) load feeds both products; with one
+//                  output the caller selects which of the pair is used.
 //  k_spmm_shift  : Q[:,l] = (L/2 - lam_l B) D[:,l] (operator of the paper's
 //                  preconditioner T_l, eq. precondition-T) with the per-column
 //                  dot products <D_l, Q_l> of the CG step fused in.
 //  k_spmv_dot    : q = A d and <d, q> for one vector (Hartree CG).
 //
-// Work mapping (wave64): a row is owned by LPR = 2^lpr_log2 lanes; each lane
-// covers V consecutive columns (one vector load of the X row slice), and
-// loops over column chunks when p > LPR*V.  A row's p values are contiguous,
-// so the LPR lanes of a row read one contiguous X row per nonzero: with
-// p = 128 in f64 a wave reads 1 KB per neighbour, fully coalesced.
-// Column indices and values are read once per lane group (the same address
-// across the group is served by one cache line).
+// Work mapping (wave64).  A row is owned by a group of LPR = 2^lpr_log2 lanes;
+// each lane covers V consecutive columns (one vector load of an X row slice)
+// and CH column chunks when p > LPR*V.  A row's p values are contiguous, so a
+// group reads one contiguous X row per nonzero (p = 128 in f64: 1 KB per
+// neighbour per wave).
+//
+// Latency: the neighbours of a row are independent, so the group first loads
+// up to LPR (column, weight) pairs with one coalesced access, then broadcasts
+// them lane to lane and issues U neighbour loads back to back before any
+// arithmetic.  Control flow around the broadcasts is uniform across the wave
+// (loop bounds use the wave's longest row; rows past n just have no entries).
 #include "common.hpp"
 
 namespace ofks {
@@ -25,7 +29,85 @@ template <typename T> struct pair_t;
 template <> struct pair_t<double> { using type = double2; };
 template <> struct pair_t<float> { using type = float2; };
 
-template <typename T, int V, int NOUT>
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// a1[ch][v] = sum_e w(e).x X[col e][c], a2 likewise with w(e).y, for the row
+// owned by this lane group (cnt entries starting at e0; cnt = 0: no row).
+// All 64 lanes of the wave must call this together.
+template <typename T, int V, int CH, int U>
+__device__ __forceinline__ void gather_row(int64_t e0, int cnt, int lpr_log2, int p,
+                                           const int32_t *__restrict__ col,
+                                           const typename pair_t<T>::type *__restrict__ w,
+                                           const T *__restrict__ X, T (&a1)[CH][V], T (&a2)[CH][V]) {
+    using P2 = typename pair_t<T>::type;
+    const int lpr = 1 << lpr_log2;
+    const int glane = threadIdx.x & (lpr - 1);
+    const int lane_in_wave = threadIdx.x & 63;
+    const int cmax = wave_max(cnt);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int v = 0; v < V; ++v) { a1[ch][v] = T(0); a2[ch][v] = T(0); }
+    for (int base = 0; base < cmax; base += lpr) {
+        int mycol = 0;
+        T mwx = T(0), mwy = T(0);
+        if (base + glane < cnt) {
+            mycol = col[e0 + base + glane];
+            const P2 ww = w[e0 + base + glane];
+            mwx = ww.x;
+            mwy = ww.y;
+        }
+        const int kend = min(lpr, cmax - base);   // uniform across the wave
+        for (int k0 = 0; k0 < kend; k0 += U) {
+            int jj[U];
+            T wx[U], wy[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int src = (lane_in_wave & ~(lpr - 1)) + ((k0 + u) & (lpr - 1));
+                jj[u] = __shfl(mycol, src, 64);
+                wx[u] = __shfl(mwx, src, 64);
+                wy[u] = __shfl(mwy, src, 64);
+                ok[u] = (k0 + u < kend) && (base + k0 + u < cnt);
+            }
+            T xb[U][CH][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch) {
+                    const int c0 = (glane + ch * lpr) * V;
+                    if (ok[u] && c0 < p) {
+                        load_vec<T, V>(X + (int64_t)jj[u] * p + c0, xb[u][ch]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) xb[u][ch][v] = T(0);
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        a1[ch][v] = fma(wx[u], xb[u][ch][v], a1[ch][v]);
+                        a2[ch][v] = fma(wy[u], xb[u][ch][v], a2[ch][v]);
+                    }
+        }
+    }
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b % 8).
+// The logical block index gives each XCD a contiguous range of rows, so the
+// neighbour rows a row reads were mostly fetched into the same XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb_padded) {
+    return (b % 8) * (nb_padded / 8) + b / 8;
+}
+
+template <typename T, int V, int CH, int U, int NOUT>
 __global__ __launch_bounds__(256) void k_spmm_pair(int64_t n, int p, int lpr_log2,
                                                   const int64_t *__restrict__ rp,
                                                   const int32_t *__restrict__ col,
@@ -33,38 +115,35 @@ __global__ __launch_bounds__(256) void k_spmm_pair(int64_t n, int p, int lpr_log
                                                   const T *__restrict__ X, T *__restrict__ Y1,
                                                   T *__restrict__ Y2, int sel) {
     const int lpr = 1 << lpr_log2;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lpr_log2;
-    const int lane = threadIdx.x & (lpr - 1);
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row = (lb * blockDim.x + threadIdx.x) >> lpr_log2;
+    const int glane = threadIdx.x & (lpr - 1);
+    int64_t e0 = 0;
+    int cnt = 0;
+    if (row < n) {
+        e0 = rp[row];
+        cnt = (int)(rp[row + 1] - e0);
+    }
+    T a1[CH][V], a2[CH][V];
+    gather_row<T, V, CH, U>(e0, cnt, lpr_log2, p, col, ab, X, a1, a2);
     if (row >= n) return;
-    const int64_t e0 = rp[row], e1 = rp[row + 1];
-    for (int c0 = lane * V; c0 < p; c0 += lpr * V) {
-        T a1[V], a2[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) { a1[v] = T(0); a2[v] = T(0); }
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t j = col[e];
-            const auto w = ab[e];
-            T x[V];
-            load_vec<T, V>(X + j * p + c0, x);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                if (NOUT == 2) {
-                    a1[v] = fma(w.x, x[v], a1[v]);
-                    a2[v] = fma(w.y, x[v], a2[v]);
-                } else {
-                    a1[v] = fma(sel ? w.y : w.x, x[v], a1[v]);
-                }
-            }
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = (glane + ch * lpr) * V;
+        if (c0 >= p) continue;
+        if (NOUT == 2) {
+            store_vec<T, V>(Y1 + row * p + c0, a1[ch]);
+            store_vec<T, V>(Y2 + row * p + c0, a2[ch]);
+        } else {
+            store_vec<T, V>(Y1 + row * p + c0, sel ? a2[ch] : a1[ch]);
         }
-        store_vec<T, V>(Y1 + row * p + c0, a1);
-        if (NOUT == 2) store_vec<T, V>(Y2 + row * p + c0, a2);
     }
 }
 
-// Persistent grid: block b handles rows {b*rpb + g + k*gridDim*rpb}; every
-// block's share and summation order are fixed by the launch shape, so the
-// per-block partial dot products (written to part[b*p + c]) are reproducible.
-template <typename T, int V, int CH>
+// Persistent grid: each wave owns a fixed sequence of row groups, so every
+// block's share and summation order are fixed by the launch shape and the
+// per-block partial dot products (part[b*p + c]) are reproducible.
+template <typename T, int V, int CH, int U>
 __global__ __launch_bounds__(256) void k_spmm_shift(int64_t n, int p, int lpr_log2,
                                                    const int64_t *__restrict__ rp,
                                                    const int32_t *__restrict__ col,
@@ -77,44 +156,58 @@ __global__ __launch_bounds__(256) void k_spmm_shift(int64_t n, int p, int lpr_lo
     const int lpr = 1 << lpr_log2;
     const int groups = blockDim.x >> lpr_log2;
     const int g = threadIdx.x >> lpr_log2;
-    const int lane = threadIdx.x & (lpr - 1);
+    const int glane = threadIdx.x & (lpr - 1);
+    const int gpw = 64 >> lpr_log2;   // row groups per wave
     double dot[CH][V];
+    T lm[CH][V];
+    bool on[CH][V];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
-        for (int v = 0; v < V; ++v) dot[ch][v] = 0.0;
-
-    for (int64_t row = (int64_t)blockIdx.x * groups + g; row < n; row += (int64_t)gridDim.x * groups) {
-        const int64_t e0 = rp[row], e1 = rp[row + 1];
+        for (int v = 0; v < V; ++v) {
+            const int c = (glane + ch * lpr) * V + v;
+            dot[ch][v] = 0.0;
+            lm[ch][v] = c < p ? lam[c] : T(0);
+            on[ch][v] = c < p ? active[c] != 0 : false;
+        }
+    // XCD x = blockIdx % 8 sweeps the row slab [x S, (x+1) S); its blocks take
+    // consecutive row groups of the slab in rounds.  rb is the first row of
+    // this wave in a round and is uniform across the wave.
+    const int64_t bpx = gridDim.x / 8;
+    const int64_t slab = ((n + 7) / 8 + groups - 1) / groups * groups;
+    const int64_t s0 = (blockIdx.x % 8) * slab;
+    const int64_t s1 = min(n, s0 + slab);
+    const int64_t stride = bpx * groups;
+    for (int64_t rb = s0 + (int64_t)(blockIdx.x / 8) * groups + (g & ~(gpw - 1)); rb < s1; rb += stride) {
+        const int64_t row = rb + (g & (gpw - 1));
+        int64_t e0 = 0;
+        int cnt = 0;
+        if (row < s1) {
+            e0 = rp[row];
+            cnt = (int)(rp[row + 1] - e0);
+        }
+        T a1[CH][V], a2[CH][V];
+        gather_row<T, V, CH, U>(e0, cnt, lpr_log2, p, col, lb, D, a1, a2);
+        if (row < s1) {
 #pragma unroll
-        for (int ch = 0; ch < CH; ++ch) {
-            const int c0 = (lane + ch * lpr) * V;
-            if (c0 >= p) continue;
-            T lm[V], acc[V];
+            for (int ch = 0; ch < CH; ++ch) {
+                const int c0 = (glane + ch * lpr) * V;
+                if (c0 >= p) continue;
+                T q[V], dv[V];
+                load_vec<T, V>(D + row * p + c0, dv);
 #pragma unroll
-            for (int v = 0; v < V; ++v) { lm[v] = lam[c0 + v]; acc[v] = T(0); }
-            for (int64_t e = e0; e < e1; ++e) {
-                const int64_t j = col[e];
-                const auto w = lb[e];
-                T x[V];
-                load_vec<T, V>(D + j * p + c0, x);
-#pragma unroll
-                for (int v = 0; v < V; ++v) acc[v] = fma(fma(-lm[v], w.y, w.x), x[v], acc[v]);
+                for (int v = 0; v < V; ++v) {
+                    q[v] = on[ch][v] ? fma(-lm[ch][v], a2[ch][v], a1[ch][v]) : T(0);
+                    dot[ch][v] += (double)dv[v] * (double)q[v];
+                }
+                store_vec<T, V>(Q + row * p + c0, q);
             }
-            T dv[V];
-            load_vec<T, V>(D + row * p + c0, dv);
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (!active[c0 + v]) acc[v] = T(0);
-            store_vec<T, V>(Q + row * p + c0, acc);
-#pragma unroll
-            for (int v = 0; v < V; ++v) dot[ch][v] += (double)dv[v] * (double)acc[v];
         }
     }
     // block reduction over row groups, fixed order
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = (lane + ch * lpr) * V;
+        const int c0 = (glane + ch * lpr) * V;
         if (c0 < p) {
 #pragma unroll
             for (int v = 0; v < V; ++v) red[g * p + c0 + v] = dot[ch][v];
@@ -175,28 +268,44 @@ static inline int lpr_log2_for(int p, int v) {
     return l > 6 ? 6 : l;
 }
 
+// Dispatch over (V, CH); U (neighbour loads in flight) shrinks as CH grows to
+// bound registers.
+#define OFKS_VCH_DISPATCH(LAUNCH)                                 \
+    do {                                                          \
+        if (v == 1 && ch <= 1) { LAUNCH(1, 1, 8); break; }        \
+        if (v == 1 && ch <= 2) { LAUNCH(1, 2, 8); break; }        \
+        if (v == 1 && ch <= 4) { LAUNCH(1, 4, 4); break; }        \
+        if (v == 1 && ch <= 8) { LAUNCH(1, 8, 2); break; }        \
+        if (v == 2 && ch <= 1) { LAUNCH(2, 1, 8); break; }        \
+        if (v == 2 && ch <= 2) { LAUNCH(2, 2, 4); break; }        \
+        if (v == 2 && ch <= 4) { LAUNCH(2, 4, 2); break; }        \
+        if (v == 2 && ch <= 8) { LAUNCH(2, 8, 1); break; }        \
+        if constexpr (sizeof(T) == 4) {                           \
+            if (v == 4 && ch <= 1) { LAUNCH(4, 1, 8); break; }    \
+            if (v == 4 && ch <= 2) { LAUNCH(4, 2, 4); break; }    \
+            if (v == 4 && ch <= 4) { LAUNCH(4, 4, 2); break; }    \
+        }                                                         \
+        return hipErrorInvalidValue;                              \
+    } while (0)
+
 template <typename T>
 hipError_t launch_spmm_pair(hipStream_t s, int64_t n, int p, const int64_t *rp, const int32_t *col,
                             const void *ab, const T *X, T *Y1, T *Y2, int sel) {
     using P2 = typename pair_t<T>::type;
     const int v = pick_v<T>(p);
     const int l2 = lpr_log2_for(p, v);
+    const int ch = (p + (v << l2) - 1) / (v << l2);
     const int64_t threads = n << l2;
     const int bs = 256;
-    const unsigned grid = (unsigned)((threads + bs - 1) / bs);
+    const unsigned grid = (unsigned)((((threads + bs - 1) / bs) + 7) / 8 * 8);   // multiple of the XCD count
     const P2 *w = (const P2 *)ab;
     const bool two = Y2 != nullptr;
-#define OFKS_SPMM_CASE(VV)                                                                   \
-    if (v == VV) {                                                                           \
-        if (two) hipLaunchKernelGGL((k_spmm_pair<T, VV, 2>), dim3(grid), dim3(bs), 0, s, n, p, l2, rp, col, w, X, Y1, Y2, sel); \
-        else hipLaunchKernelGGL((k_spmm_pair<T, VV, 1>), dim3(grid), dim3(bs), 0, s, n, p, l2, rp, col, w, X, Y1, Y2, sel);   \
-        return hipGetLastError();                                                            \
-    }
-    OFKS_SPMM_CASE(1)
-    OFKS_SPMM_CASE(2)
-    if constexpr (sizeof(T) == 4) { OFKS_SPMM_CASE(4) }
-#undef OFKS_SPMM_CASE
-    return hipErrorInvalidValue;
+#define OFKS_PAIR(VV, CC, UU)                                                                                 \
+    if (two) hipLaunchKernelGGL((k_spmm_pair<T, VV, CC, UU, 2>), dim3(grid), dim3(bs), 0, s, n, p, l2, rp, col, w, X, Y1, Y2, sel); \
+    else hipLaunchKernelGGL((k_spmm_pair<T, VV, CC, UU, 1>), dim3(grid), dim3(bs), 0, s, n, p, l2, rp, col, w, X, Y1, Y2, sel)
+    OFKS_VCH_DISPATCH(OFKS_PAIR);
+#undef OFKS_PAIR
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -204,32 +313,18 @@ hipError_t launch_spmm_shift(hipStream_t s, int grid, int64_t n, int p, const in
                              const int32_t *col, const void *lb, const T *lam, const uint8_t *active,
                              const T *D, T *Q, double *part) {
     using P2 = typename pair_t<T>::type;
+    if (grid % 8 != 0 || grid < 8) return hipErrorInvalidValue;   // whole XCD slabs
     const int v = pick_v<T>(p);
     const int l2 = lpr_log2_for(p, v);
-    const int chunks = (p + (v << l2) - 1) / (v << l2);
+    const int ch = (p + (v << l2) - 1) / (v << l2);
     const int bs = 256;
     const size_t shm = (size_t)(bs >> l2) * p * sizeof(double);
     const P2 *w = (const P2 *)lb;
-#define OFKS_SHIFT_CASE(VV, CC)                                                              \
-    if (v == VV && chunks <= CC) {                                                           \
-        hipLaunchKernelGGL((k_spmm_shift<T, VV, CC>), dim3(grid), dim3(bs), shm, s, n, p, l2, rp, col, w, lam, active, D, Q, part); \
-        return hipGetLastError();                                                            \
-    }
-    OFKS_SHIFT_CASE(1, 1)
-    OFKS_SHIFT_CASE(1, 2)
-    OFKS_SHIFT_CASE(1, 4)
-    OFKS_SHIFT_CASE(1, 8)
-    OFKS_SHIFT_CASE(2, 1)
-    OFKS_SHIFT_CASE(2, 2)
-    OFKS_SHIFT_CASE(2, 4)
-    OFKS_SHIFT_CASE(2, 8)
-    if constexpr (sizeof(T) == 4) {
-        OFKS_SHIFT_CASE(4, 1)
-        OFKS_SHIFT_CASE(4, 2)
-        OFKS_SHIFT_CASE(4, 4)
-    }
-#undef OFKS_SHIFT_CASE
-    return hipErrorInvalidValue;
+#define OFKS_SHIFT(VV, CC, UU) \
+    hipLaunchKernelGGL((k_spmm_shift<T, VV, CC, UU>), dim3(grid), dim3(bs), shm, s, n, p, l2, rp, col, w, lam, active, D, Q, part)
+    OFKS_VCH_DISPATCH(OFKS_SHIFT);
+#undef OFKS_SHIFT
+    return hipGetLastError();
 }
 
 hipError_t launch_spmv_dot(hipStream_t s, int grid, int64_t n, const int64_t *rp, const int32_t *col,

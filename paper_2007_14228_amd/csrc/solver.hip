@@ -54,12 +54,18 @@ struct GradArgs {
     double *part;
 };
 enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2 };
+struct GramPlan {
+    int mt, nt, gx, gy;
+    int64_t splits, rows_per_split;
+};
+GramPlan gram_plan(int64_t n, int p, int target_blocks);
 template <typename T>
-hipError_t launch_gram(hipStream_t, int64_t, int, int, const T *, const T *, const T *, double *, int *);
+hipError_t launch_gram(hipStream_t, int64_t, int, const GramPlan &, const T *, const T *, const T *, double *, size_t);
 hipError_t launch_colsum(hipStream_t, int64_t, int64_t, const double *, double *);
 template <typename T>
 hipError_t launch_rowgemm(hipStream_t, int, int64_t, int, int, int, const T *, const T *, const T *, T *,
                           GradArgs, int *);
+int rowgemm_tile_cols(int N);
 template <typename T>
 hipError_t launch_pcg_xr(hipStream_t, int, int64_t, int, int, const T *, const uint8_t *, const double *,
                          const double *, const T *, const T *, const T *, T *, T *, double *);
@@ -188,7 +194,7 @@ struct ofks_ctx {
     size_t hbuf_cap = 0;
     char *hup = nullptr;     // pinned upload staging, consumed by a cursor reset at each sync
     size_t hup_cap = 0, hup_off = 0;
-    int grid = 1024;         // persistent grid for partial-sum kernels
+    int grid = 2048;         // persistent grid for partial-sum kernels
     int gemm_rows = 1024;
 
     int k = 0;
@@ -416,15 +422,14 @@ template <typename T>
 int gram(ofks_ctx *c, const T *X, const T *BX, const T *HX, std::vector<double> &St, std::vector<double> &Lt) {
     const int p = c->p;
     const size_t pp2 = (size_t)p * 2 * p;
-    // launch_gram uses at most max(target, tiles) * 64 * 64 partial values
-    const int target = 2048;
-    CHK(ensure_part(c, std::max<size_t>(pp2, (size_t)target * 64 * 64)));
-    int ns = 0;
+    // size the split-K partials from the launch plan before launching
+    const GramPlan plan = gram_plan(c->n, p, 2048);
+    CHK(ensure_part(c, (size_t)plan.splits * pp2));
+    const int64_t ns = plan.splits;
     {
         Scope sc(c, "gram");
-        HIPCHK(launch_gram<T>(c->stream, c->n, p, target, X, BX, HX, c->part, &ns));
+        HIPCHK(launch_gram<T>(c->stream, c->n, p, plan, X, BX, HX, c->part, c->part_cap));
     }
-    if ((size_t)ns * pp2 > c->part_cap) return fail(c, OFKS_EINVAL, "gram: partial buffer too small");
     HIPCHK(launch_colsum(c->stream, ns, (int64_t)pp2, c->part, c->red));
     std::vector<double> G;
     CHK(download(c, G, c->red, pp2));
@@ -639,7 +644,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     int gx = 0;
     const int epi = any_active ? EPI_GRAD_PCG : EPI_GRAD;
     {
-        const int tc = (2 * p <= 16) ? 16 : ((2 * p <= 32) ? 32 : 64);
+        const int tc = rowgemm_tile_cols(2 * p);
         const int gy = (2 * p + tc - 1) / tc;
         CHK(ensure_part(c, (size_t)c->gemm_rows * gy * (1 + p)));
         {
@@ -699,14 +704,14 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
             HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
             HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, c->rz, B.alpha));
             {
-                Scope sc(c, "pcg_axpy");
+                Scope sc(c, "pcg_xr");
                 HIPCHK(launch_pcg_xr<T>(c->stream, c->grid, n, p, it == 0, B.alpha, c->active, c->lhd, c->bd,
                                         B.lam, B.D, B.HX, B.P, B.R, c->part));
             }
             HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
             if (it + 1 < c->prm.pcg_iters) {
                 HIPCHK(launch_pcg_scalars<T>(c->stream, p, 1, c->red, c->rz, B.beta));
-                Scope sc(c, "pcg_axpy");
+                Scope sc(c, "pcg_dir");
                 HIPCHK(launch_pcg_dir<T>(c->stream, n, p, B.beta, c->active, c->lhd, c->bd, B.lam, B.R, B.D));
             }
         }
@@ -1312,7 +1317,7 @@ int ofks_get_density(ofks_ctx *c, double *dev_rho) {
 int ofks_spmm(ofks_ctx *c, int32_t p, const double *X, double *HX, double *BX) {
     if (!c) return OFKS_EINVAL;
     if (!c->has_system) return fail(c, OFKS_ESTATE, "spmm: no system");
-    if (p <= 0 || !X || !HX || !BX) return fail(c, OFKS_EINVAL, "spmm: bad arguments");
+    if (p <= 0 || p > 1024 || !X || !HX || !BX) return fail(c, OFKS_EINVAL, "spmm: bad arguments");
     HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, X, HX, BX, 0));
     return sync(c);
 }
@@ -1320,7 +1325,7 @@ int ofks_spmm(ofks_ctx *c, int32_t p, const double *X, double *HX, double *BX) {
 int ofks_gram(ofks_ctx *c, int32_t p, const double *X, const double *HX, const double *BX, double *S, double *L0) {
     if (!c) return OFKS_EINVAL;
     if (!c->has_system) return fail(c, OFKS_ESTATE, "gram: no system");
-    if (p <= 0 || !X || !HX || !BX || !S || !L0) return fail(c, OFKS_EINVAL, "gram: bad arguments");
+    if (p <= 0 || p > 1024 || !X || !HX || !BX || !S || !L0) return fail(c, OFKS_EINVAL, "gram: bad arguments");
     const int keep = c->p;
     c->p = p;
     std::vector<double> St, Lt;
@@ -1335,7 +1340,7 @@ int ofks_gram(ofks_ctx *c, int32_t p, const double *X, const double *HX, const d
 int ofks_precondition(ofks_ctx *c, int32_t p, const double *lam, const double *G, double *P) {
     if (!c) return OFKS_EINVAL;
     if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "precondition: needs L/2 and B");
-    if (p <= 0 || !lam || !G || !P) return fail(c, OFKS_EINVAL, "precondition: bad arguments");
+    if (p <= 0 || p > 1024 || !lam || !G || !P) return fail(c, OFKS_EINVAL, "precondition: bad arguments");
     const int m = c->prm.pcg_iters;
     if (m < 1) return fail(c, OFKS_EINVAL, "precondition: pcg_iters must be >= 1");
     const int64_t n = c->n;
@@ -1387,7 +1392,7 @@ int ofks_build_hamiltonian(ofks_ctx *c, int32_t p, const double *X, double *rho_
                            double *U, double *parts) {
     if (!c) return OFKS_EINVAL;
     if (!c->assembled) return fail(c, OFKS_ESTATE, "build_hamiltonian: needs an assembled mesh");
-    if (p <= 0 || !X) return fail(c, OFKS_EINVAL, "build_hamiltonian: bad arguments");
+    if (p <= 0 || p > 1024 || !X) return fail(c, OFKS_EINVAL, "build_hamiltonian: bad arguments");
     if (!c->has_params) ofks_default_params(&c->prm);
     double *ones = nullptr;
     CHK(dalloc(c, &ones, p));
