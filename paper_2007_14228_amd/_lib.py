@@ -89,11 +89,17 @@ SIGNATURES = [
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Loads the HIP library; raises if it has not been built."""
+def load(path: str = None):
+    """Loads the HIP library; raises if it has not been built.
+
+    torch is imported first so that libofks.so binds to the HIP runtime that
+    torch has already loaded: one runtime per process, shared streams and
+    device memory."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (loads the HIP runtime the library must share)
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2007_14228_amd.build`")
     lib = ctypes.CDLL(path)

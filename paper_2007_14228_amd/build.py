@@ -23,14 +23,16 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, extra_flags=(), out: str = LIB, build_dir: str = None) -> str:
+    """Compiles every HIP source and links libofks.so (extra_flags: additional
+    compiler options such as tuning macros; out: output path)."""
     objs = []
-    build_dir = os.path.join(HERE, "_build")
+    build_dir = build_dir or os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     common = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
               # packed FP32 arithmetic stays off (see the design notes)
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-I", os.path.join(os.path.dirname(HERE), "include")]
+              "-I", os.path.join(os.path.dirname(HERE), "include")] + list(extra_flags)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     procs = []
     for src in srcs:
@@ -40,8 +42,8 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     failed = []
     for src, pr in procs:
-        out, _ = pr.communicate()
-        text = out.decode(errors="replace")
+        log, _ = pr.communicate()
+        text = log.decode(errors="replace")
         # the host pass does not know the packed-fp32 feature; that note is harmless
         lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l and l.strip()]
         if pr.returncode != 0:
@@ -51,10 +53,10 @@ def build(verbose: bool = False) -> str:
     if failed:
         msg = "\n".join(f"--- {s}\n{t}" for s, t in failed)
         raise RuntimeError(f"HIP build failed:\n{msg}")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     subprocess.check_call([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

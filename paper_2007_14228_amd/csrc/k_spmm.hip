@@ -23,7 +23,35 @@
 // (loop bounds use the wave's longest row; rows past n just have no entries).
 #include "common.hpp"
 
+// Tuning: neighbour loads in flight per wave for one-column-chunk rows, and
+// whether streamed data (CSR entries read once, outputs written once) use
+// non-temporal accesses so that they do not evict reused X rows from L2.
+#ifndef OFKS_SPMM_U
+#define OFKS_SPMM_U 16
+#endif
+#ifndef OFKS_SPMM_NT
+#define OFKS_SPMM_NT 1
+#endif
+
 namespace ofks {
+
+template <typename T> __device__ __forceinline__ T stream_load(const T *p) {
+#if OFKS_SPMM_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void stream_store_vec(T *__restrict__ p, const T (&in)[V]) {
+#if OFKS_SPMM_NT
+#pragma unroll
+    for (int i = 0; i < V; ++i) __builtin_nontemporal_store(in[i], p + i);
+#else
+    store_vec<T, V>(p, in);
+#endif
+}
 
 template <typename T> struct pair_t;
 template <> struct pair_t<double> { using type = double2; };
@@ -221,6 +249,159 @@ __global__ __launch_bounds__(256) void k_spmm_shift(int64_t n, int p, int lpr_lo
     }
 }
 
+// One wave per row (used when a row's p values need all 64 lanes).  The row
+// index is wave-uniform, so the row bounds, column indices and weights are
+// scalar loads, and all U neighbour loads of a row go out as one batch before
+// the arithmetic.
+//
+// Locality: with a locality-preserving node numbering the neighbours of a
+// row have nearby numbers, so the rows in flight on one XCD must be a narrow
+// window of consecutive rows for their neighbour rows to stay in that XCD's
+// L2.  Rows go to XCDs in contiguous slabs (block b runs on XCD b % 8).
+//  MODE 0 (Y1 = A1 X, Y2 = A2 X, or A2 X into Y1 when sel = 1): one row per
+//    wave, blocks in slab order, so the dispatcher sweeps each slab forward.
+//  MODE 1 (shifted operator, per-block partial dots part[block][p]):
+//    persistent; the launcher sizes the grid to the blocks that can be
+//    resident at once, and round r of block j takes rows base + 4 (r B + j),
+//    so each round sweeps a window of 4 B consecutive rows per XCD.
+template <typename T, int V, int CH, int U, int MODE>
+__global__ __launch_bounds__(256) void k_spmm_wave(int64_t n, int p, const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col,
+                                                  const typename pair_t<T>::type *__restrict__ w,
+                                                  const T *__restrict__ X, T *__restrict__ Y1,
+                                                  T *__restrict__ Y2, int sel, const T *__restrict__ lam,
+                                                  const uint8_t *__restrict__ active,
+                                                  double *__restrict__ part) {
+    using P2 = typename pair_t<T>::type;
+    __shared__ double red[4][64 * V * CH];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t row, s1, stride;
+    if (MODE == 0) {
+        row = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+        s1 = n;
+        stride = n;   // one row
+    } else {
+        const int64_t bpx = gridDim.x / 8;
+        const int64_t slab = ((n + 7) / 8 + 3) / 4 * 4;
+        const int64_t s0 = (blockIdx.x % 8) * slab;
+        s1 = min(n, s0 + slab);
+        row = s0 + (int64_t)(blockIdx.x / 8) * 4 + wave;
+        stride = bpx * 4;
+    }
+    double dot[CH][V];
+    T lm[CH][V];
+    bool on[CH][V];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int c = (lane + ch * 64) * V + v;
+            dot[ch][v] = 0.0;
+            if (MODE == 1) {
+                lm[ch][v] = c < p ? lam[c] : T(0);
+                on[ch][v] = c < p ? active[c] != 0 : false;
+            }
+        }
+    for (; row < s1; row += stride) {
+        const int64_t e0 = rp[row], e1 = rp[row + 1];
+        T a1[CH][V], a2[CH][V];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int v = 0; v < V; ++v) { a1[ch][v] = T(0); a2[ch][v] = T(0); }
+        for (int64_t e = e0; e < e1; e += U) {
+            const int m = (int)min((int64_t)U, e1 - e);
+            int jj[U];
+            T wx[U], wy[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (u < m) {
+                    jj[u] = stream_load(col + e + u);
+                    wx[u] = stream_load(&w[e + u].x);
+                    wy[u] = stream_load(&w[e + u].y);
+                } else {
+                    jj[u] = 0;
+                    wx[u] = T(0);
+                    wy[u] = T(0);
+                }
+            }
+            T xb[U][CH][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch) {
+                    const int c0 = (lane + ch * 64) * V;
+                    if (u < m && c0 < p) {
+                        load_vec<T, V>(X + (int64_t)jj[u] * p + c0, xb[u][ch]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) xb[u][ch][v] = T(0);
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        a1[ch][v] = fma(wx[u], xb[u][ch][v], a1[ch][v]);
+                        a2[ch][v] = fma(wy[u], xb[u][ch][v], a2[ch][v]);
+                    }
+        }
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const int c0 = (lane + ch * 64) * V;
+            if (c0 >= p) continue;
+            if (MODE == 0) {
+                if (Y2) {
+                    stream_store_vec<T, V>(Y1 + row * p + c0, a1[ch]);
+                    stream_store_vec<T, V>(Y2 + row * p + c0, a2[ch]);
+                } else {
+                    stream_store_vec<T, V>(Y1 + row * p + c0, sel ? a2[ch] : a1[ch]);
+                }
+            } else {
+                T q[V], dv[V];
+                load_vec<T, V>(X + row * p + c0, dv);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    q[v] = on[ch][v] ? fma(-lm[ch][v], a2[ch][v], a1[ch][v]) : T(0);
+                    dot[ch][v] += (double)dv[v] * (double)q[v];
+                }
+                stream_store_vec<T, V>(Y1 + row * p + c0, q);
+            }
+        }
+    }
+    if (MODE == 1) {
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int v = 0; v < V; ++v) red[wave][(lane + ch * 64) * V + v] = dot[ch][v];
+        __syncthreads();
+        for (int c = threadIdx.x; c < p; c += blockDim.x)
+            part[(int64_t)blockIdx.x * p + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+}
+
+// blocks of the non-persistent mode (one row per wave), whole XCD slabs
+int64_t spmm_wave_blocks(int64_t n) { return ((n + 3) / 4 + 7) / 8 * 8; }
+
+// Persistent grid of the shifted mode: the blocks that fit on the device at
+// once (occupancy of this kernel instance), a multiple of 8 and at most cap.
+template <typename K> int resident_grid(K kernel, int cap) {
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0);
+        int g = cus * (per > 0 ? per : 1);
+        g = g / 8 * 8;
+        cached = g < 8 ? 8 : g;
+    }
+    return cached < cap ? cached : cap;
+}
+
 // Scalar SpMV with the dot <d, A d> fused (Hartree CG); persistent grid,
 // one lane per row, per-block partial written to part[block].
 __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__restrict__ rp,
@@ -295,10 +476,30 @@ hipError_t launch_spmm_pair(hipStream_t s, int64_t n, int p, const int64_t *rp, 
     const int v = pick_v<T>(p);
     const int l2 = lpr_log2_for(p, v);
     const int ch = (p + (v << l2) - 1) / (v << l2);
+    const P2 *w = (const P2 *)ab;
+    if (l2 == 6) {
+        const unsigned grid = (unsigned)spmm_wave_blocks(n);
+#define OFKS_WAVE0(VV, CC)                                                                                   \
+    hipLaunchKernelGGL((k_spmm_wave<T, VV, CC, (CC >= 8 ? 2 : OFKS_SPMM_U / CC), 0>), dim3(grid), dim3(256), 0, s, n, p, rp, col, w, X, Y1, Y2, \
+                       sel, (const T *)nullptr, (const uint8_t *)nullptr, (double *)nullptr)
+        if (v == 1 && ch == 1) OFKS_WAVE0(1, 1);
+        else if (v == 1 && ch <= 2) OFKS_WAVE0(1, 2);
+        else if (v == 2 && ch == 1) OFKS_WAVE0(2, 1);
+        else if (v == 2 && ch <= 2) OFKS_WAVE0(2, 2);
+        else if (v == 2 && ch <= 4) OFKS_WAVE0(2, 4);
+        else if (v == 2 && ch <= 8) OFKS_WAVE0(2, 8);
+        else if constexpr (sizeof(T) == 4) {
+            if (v == 4 && ch == 1) OFKS_WAVE0(4, 1);
+            else if (v == 4 && ch <= 2) OFKS_WAVE0(4, 2);
+            else if (v == 4 && ch <= 4) OFKS_WAVE0(4, 4);
+            else return hipErrorInvalidValue;
+        } else return hipErrorInvalidValue;
+#undef OFKS_WAVE0
+        return hipGetLastError();
+    }
     const int64_t threads = n << l2;
     const int bs = 256;
     const unsigned grid = (unsigned)((((threads + bs - 1) / bs) + 7) / 8 * 8);   // multiple of the XCD count
-    const P2 *w = (const P2 *)ab;
     const bool two = Y2 != nullptr;
 #define OFKS_PAIR(VV, CC, UU)                                                                                 \
     if (two) hipLaunchKernelGGL((k_spmm_pair<T, VV, CC, UU, 2>), dim3(grid), dim3(bs), 0, s, n, p, l2, rp, col, w, X, Y1, Y2, sel); \
@@ -308,18 +509,45 @@ hipError_t launch_spmm_pair(hipStream_t s, int64_t n, int p, const int64_t *rp, 
     return hipGetLastError();
 }
 
+// Launches at most `grid` blocks (the caller's partial buffer holds grid * p
+// values) and reports the number used in *blocks_used.
 template <typename T>
 hipError_t launch_spmm_shift(hipStream_t s, int grid, int64_t n, int p, const int64_t *rp,
                              const int32_t *col, const void *lb, const T *lam, const uint8_t *active,
-                             const T *D, T *Q, double *part) {
+                             const T *D, T *Q, double *part, int *blocks_used) {
     using P2 = typename pair_t<T>::type;
     if (grid % 8 != 0 || grid < 8) return hipErrorInvalidValue;   // whole XCD slabs
+    *blocks_used = grid;
     const int v = pick_v<T>(p);
     const int l2 = lpr_log2_for(p, v);
     const int ch = (p + (v << l2) - 1) / (v << l2);
     const int bs = 256;
     const size_t shm = (size_t)(bs >> l2) * p * sizeof(double);
     const P2 *w = (const P2 *)lb;
+    if (l2 == 6) {
+#define OFKS_WAVE1(VV, CC)                                                                                   \
+    do {                                                                                                     \
+        auto kfn = k_spmm_wave<T, VV, CC, (CC >= 8 ? 2 : OFKS_SPMM_U / CC), 1>;                                       \
+        const int wgrid = resident_grid(kfn, grid);                                                          \
+        *blocks_used = wgrid;                                                                                \
+        hipLaunchKernelGGL(kfn, dim3(wgrid), dim3(256), 0, s, n, p, rp, col, w, D, Q, (T *)nullptr, 0, lam,   \
+                           active, part);                                                                    \
+    } while (0)
+        if (v == 1 && ch == 1) OFKS_WAVE1(1, 1);
+        else if (v == 1 && ch <= 2) OFKS_WAVE1(1, 2);
+        else if (v == 2 && ch == 1) OFKS_WAVE1(2, 1);
+        else if (v == 2 && ch <= 2) OFKS_WAVE1(2, 2);
+        else if (v == 2 && ch <= 4) OFKS_WAVE1(2, 4);
+        else if (v == 2 && ch <= 8) OFKS_WAVE1(2, 8);
+        else if constexpr (sizeof(T) == 4) {
+            if (v == 4 && ch == 1) OFKS_WAVE1(4, 1);
+            else if (v == 4 && ch <= 2) OFKS_WAVE1(4, 2);
+            else if (v == 4 && ch <= 4) OFKS_WAVE1(4, 4);
+            else return hipErrorInvalidValue;
+        } else return hipErrorInvalidValue;
+#undef OFKS_WAVE1
+        return hipGetLastError();
+    }
 #define OFKS_SHIFT(VV, CC, UU) \
     hipLaunchKernelGGL((k_spmm_shift<T, VV, CC, UU>), dim3(grid), dim3(bs), shm, s, n, p, l2, rp, col, w, lam, active, D, Q, part)
     OFKS_VCH_DISPATCH(OFKS_SHIFT);
@@ -339,9 +567,9 @@ template hipError_t launch_spmm_pair<float>(hipStream_t, int64_t, int, const int
                                             const void *, const float *, float *, float *, int);
 template hipError_t launch_spmm_shift<double>(hipStream_t, int, int64_t, int, const int64_t *,
                                               const int32_t *, const void *, const double *,
-                                              const uint8_t *, const double *, double *, double *);
+                                              const uint8_t *, const double *, double *, double *, int *);
 template hipError_t launch_spmm_shift<float>(hipStream_t, int, int64_t, int, const int64_t *,
                                              const int32_t *, const void *, const float *,
-                                             const uint8_t *, const float *, float *, double *);
+                                             const uint8_t *, const float *, float *, double *, int *);
 
 }  // namespace ofks

@@ -38,7 +38,7 @@ hipError_t launch_spmm_pair(hipStream_t, int64_t, int, const int64_t *, const in
                             T *, T *, int);
 template <typename T>
 hipError_t launch_spmm_shift(hipStream_t, int, int64_t, int, const int64_t *, const int32_t *, const void *,
-                             const T *, const uint8_t *, const T *, T *, double *);
+                             const T *, const uint8_t *, const T *, T *, double *, int *);
 hipError_t launch_spmv_dot(hipStream_t, int, int64_t, const int64_t *, const int32_t *, const double *,
                            const double *, double *, double *);
 // (k_blas.hip)
@@ -270,6 +270,13 @@ int ensure_host(ofks_ctx *c, size_t doubles) {
     return OFKS_OK;
 }
 
+int ensure_part(ofks_ctx *c, size_t doubles);
+
+// Largest per-block partial buffer any kernel of an iteration needs for this
+// p, reserved once so that no reallocation happens while kernels that hold
+// the pointer are queued.
+size_t partials_needed(ofks_ctx *c, int p);
+
 int ensure_part(ofks_ctx *c, size_t doubles) {
     if (c->part_cap >= doubles) return OFKS_OK;
     HIPCHK(hipStreamSynchronize(c->stream));   // kernels in flight may still use the old buffer
@@ -441,6 +448,17 @@ int gram(ofks_ctx *c, const T *X, const T *BX, const T *HX, std::vector<double> 
             Lt[a * p + b] = G[(size_t)a * 2 * p + p + b];
         }
     return OFKS_OK;
+}
+
+size_t partials_needed(ofks_ctx *c, int p) {
+    const GramPlan plan = gram_plan(c->n, p, 2048);
+    const int tc = rowgemm_tile_cols(2 * p);
+    const size_t gy = (2 * p + tc - 1) / tc;
+    size_t need = (size_t)plan.splits * p * 2 * p;
+    need = std::max(need, (size_t)c->gemm_rows * gy * (1 + p));
+    need = std::max(need, (size_t)c->grid * std::max(p, 5));
+    need = std::max(need, (size_t)3 * 1024);
+    return need;
 }
 
 // column sums of A .* B over rows (FP64)
@@ -640,13 +658,14 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     CHK(upload_bytes(c, c->active, act.data(), p));
 
     // G, R (kkt) and the start of the CG
-    GradArgs ga{B.HX, B.P, B.R, B.D, c->lhd, c->bd, B.lam, c->active, c->part};
     int gx = 0;
     const int epi = any_active ? EPI_GRAD_PCG : EPI_GRAD;
     {
         const int tc = rowgemm_tile_cols(2 * p);
         const int gy = (2 * p + tc - 1) / tc;
         CHK(ensure_part(c, (size_t)c->gemm_rows * gy * (1 + p)));
+        // built after the partial buffer is final: it carries that pointer
+        GradArgs ga{B.HX, B.P, B.R, B.D, c->lhd, c->bd, B.lam, c->active, c->part};
         {
             Scope sc(c, "update_a");
             HIPCHK(launch_rowgemm<T>(c->stream, epi, n, p, 2 * p, c->gemm_rows, B.BX, B.dinv, B.CC, nullptr, ga,
@@ -684,7 +703,9 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         st->precond_used = c->prm.precond;
         st->fell_back = 0;
     }
-    if (!std::isfinite(rel)) return fail(c, OFKS_ENONFINITE, "non-finite residual");
+    if (!std::isfinite(rel))
+        return fail(c, OFKS_ENONFINITE, "non-finite residual at k=%d: kkt=%g fea=%g kkt0=%g", c->k, kkt, fea,
+                    c->kkt0);
     if (rel < c->prm.tol || c->k >= c->prm.max_iter) {
         *stop = true;
         if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -696,12 +717,13 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         HIPCHK(hipMemcpyAsync(c->rz, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         CHK(ensure_part(c, (size_t)c->grid * p));
         for (int it = 0; it < c->prm.pcg_iters; ++it) {
+            int used = 0;
             {
                 Scope sc(c, "spmm_shift");
                 HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, n, p, c->rp, c->col, lbT<T>(c), B.lam, c->active,
-                                            B.D, B.HX, c->part));
+                                            B.D, B.HX, c->part, &used));
             }
-            HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+            HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
             HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, c->rz, B.alpha));
             {
                 Scope sc(c, "pcg_xr");
@@ -1143,6 +1165,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     c->prec = c->prm.precision;
     CHK(dalloc(c, &c->active, p));
     CHK(dalloc(c, &c->rz, p));
+    CHK(ensure_part(c, partials_needed(c, p)));
     CHK(alloc_blocks<double>(c));
     Blocks<double> &B = c->b64;
     HIPCHK(hipMemcpyAsync(B.Xt, X0, (size_t)c->n * p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1195,7 +1218,11 @@ int ofks_step(ofks_ctx *c, int32_t max_steps, ofks_iter_stats *stats, int32_t *n
         ofks_iter_stats st{};
         if (c->prec == OFKS_F64) rc = iterate<double>(c, &st, &stop);
         else rc = iterate<float>(c, &st, &stop);
-        if (rc < 0) break;
+        if (rc < 0) {
+            // report what the failing iteration evaluated before the error
+            if (stats && st.k == c->k && std::isfinite(st.kkt + st.fea)) stats[ns++] = st;
+            break;
+        }
         if (stats) stats[ns] = st;
         ++ns;
         if (stop) {
@@ -1365,8 +1392,10 @@ int ofks_precondition(ofks_ctx *c, int32_t p, const double *lam, const double *G
     HIPCHK(launch_pcg_init<double>(c->stream, c->grid, n, p, act, c->lhd, c->bd, lamd, G, R, D, P, c->part));
     HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, rzd));
     for (int it = 0; it < m; ++it) {
-        HIPCHK(launch_spmm_shift<double>(c->stream, c->grid, n, p, c->rp, c->col, c->lb, lamd, act, D, Q, c->part));
-        HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+        int used = 0;
+        HIPCHK(launch_spmm_shift<double>(c->stream, c->grid, n, p, c->rp, c->col, c->lb, lamd, act, D, Q, c->part,
+                                         &used));
+        HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
         HIPCHK(launch_pcg_scalars<double>(c->stream, p, 0, c->red, rzd, alpha));
         HIPCHK(launch_pcg_xr<double>(c->stream, c->grid, n, p, it == 0, alpha, act, c->lhd, c->bd, lamd, D, Q, P, R,
                                      c->part));

@@ -95,7 +95,7 @@ def test_gram(p, graded):
     assert _relerr(L0, X.T @ HX) < 1e-12
 
 
-@pytest.mark.parametrize("p", [1, 5, 16])
+@pytest.mark.parametrize("p", [1, 5, 16, 128, 130])
 def test_preconditioner_cg(p, graded):
     w, d = graded
     print(f"[gpu] precondition p={p}", flush=True)

@@ -123,9 +123,13 @@ def test_gradient_matches_finite_differences_of_the_augmented_lagrangian(c1):
     BX = prob.bx(X)
     S = X.T @ BX
     G = prob.hx(X) - BX @ Lam + beta * BX @ (S - I)
-    eps = 1e-5
-    fd = (Lb(X + eps * Zd) - Lb(X - eps * Zd)) / (2 * eps)
-    assert abs(fd - np.sum(G * Zd)) < 1e-7 * max(1.0, abs(fd))
+    g = float(np.sum(G * Zd))
+    errs = []
+    for eps in (4e-6, 2e-6):
+        fd = (Lb(X + eps * Zd) - Lb(X - eps * Zd)) / (2 * eps)
+        errs.append(abs(fd - g))
+    assert errs[1] < 1e-7 * max(1.0, abs(g))
+    assert 3.0 < errs[0] / errs[1] < 5.0           # central differences: O(eps^2)
 
 
 def test_preconditioner_pcg_reaches_the_direct_solve(c1):

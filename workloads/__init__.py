@@ -148,8 +148,25 @@ for _perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
     _KUHN_PATHS.append(_path)
 
 
-def kuhn_mesh(xs: np.ndarray, ys: np.ndarray, zs: np.ndarray) -> Mesh:
-    """Tensor grid of nodes (x fastest) split into 6 tetrahedra per cell."""
+def _morton_rank(I: np.ndarray, J: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Rank of each (i, j, k) along the Z-order (bit-interleaved) curve."""
+    code = np.zeros(I.shape, dtype=np.uint64)
+    for b in range(21):
+        for d, A in enumerate((I, J, K)):
+            code |= ((A.astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + d)
+    order = np.argsort(code, kind="stable")
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    return rank
+
+
+def kuhn_mesh(xs: np.ndarray, ys: np.ndarray, zs: np.ndarray, order: str = "morton") -> Mesh:
+    """Tensor grid split into 6 tetrahedra per cell.
+
+    order = "morton": nodes are numbered along the Z-order curve of their grid
+    indices, so that the neighbours of a node have nearby numbers at every
+    scale (the locality a reordered unstructured mesh would have);
+    order = "lex": x fastest, then y, then z."""
     nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
     X, Y, Zc = np.meshgrid(xs, ys, zs, indexing="ij")
     # node id = i + (nx+1) * (j + (ny+1) * k)
@@ -178,6 +195,18 @@ def kuhn_mesh(xs: np.ndarray, ys: np.ndarray, zs: np.ndarray) -> Mesh:
     J = J.transpose(2, 1, 0).ravel()
     K = K.transpose(2, 1, 0).ravel()
     bnd = (I == 0) | (I == nx) | (J == 0) | (J == ny) | (K == 0) | (K == nz)
+    if order == "morton":
+        rank = _morton_rank(I, J, K)              # new id of lexicographic node
+        xyz_new = np.empty_like(xyz)
+        xyz_new[rank] = xyz
+        bnd_new = np.empty_like(bnd)
+        bnd_new[rank] = bnd
+        tets = rank[tets].astype(np.int32)
+        # tetrahedra follow the order of their first vertex
+        tets = tets[np.argsort(tets.min(axis=1), kind="stable")]
+        xyz, bnd = xyz_new, bnd_new
+    elif order != "lex":
+        raise ValueError(order)
     return Mesh(xyz=xyz, tets=tets, dirichlet=bnd.astype(np.uint8), cells=(nx, ny, nz))
 
 
