@@ -189,6 +189,47 @@ int ofks_precondition(ofks_ctx *ctx, int32_t p, const double *lam, const double 
 int ofks_build_hamiltonian(ofks_ctx *ctx, int32_t p, const double *X, double *rho_q,
                            double *eps_q, double *vxc_q, double *U, double *parts);
 
+/* ---- learned pointwise preconditioner (not in the paper) --------------------
+ *
+ * With params.precond = OFKS_PRECOND_LEARNED the step uses
+ *   P_il = exp(f(x_il)) J_il G_il,  f = MLP 4 -> 32 (tanh) -> 1 (FP32),
+ *   x_il = standardized [log(L_ii/2), log B_ii, (H_ii - L_ii/2)/B_ii, g_il/rms(g_l)],
+ *   J_il = 1/(L_ii/2 - Lambda_ll B_ii) if Lambda_ll < 0, else 1
+ * and falls back to the paper preconditioner (eq. precondition-T) for
+ * fallback_hold iterations whenever the energy of an iterate exceeds the
+ * minimum of the previous fallback_window iterates.  Weight vector (193
+ * floats): [W1 (32 x 4 row-major), b1 (32), W2 (32), b2 (1)]; norm (8 floats):
+ * feature means then standard deviations (all > 0). */
+int ofks_lp_set_weights(ofks_ctx *ctx, const float *host_w, const float *host_norm);
+
+/* Training-sample collection: while dev_buf != NULL, every iteration that
+ * applies the paper preconditioner appends, for every row_stride-th row and
+ * all columns, one sample of 8 floats [4 raw features, a = J g, t = (T^-1 g),
+ * w = 1/mean_i t_il^2, 0] to dev_buf (device, capacity cap samples).
+ * A new dev_buf restarts the count at zero; dev_buf = NULL stops collection
+ * and leaves the count of the last buffer readable through
+ * ofks_lp_collected.  The buffer is caller-owned. */
+int ofks_lp_collect(ofks_ctx *ctx, int64_t row_stride, float *dev_buf, int64_t cap);
+int ofks_lp_collected(ofks_ctx *ctx, int64_t *count);
+
+/* Trains on m device samples: standardization from the samples (norm_out,
+ * host f32[8]), then `epochs` full-batch Adam steps (lr, betas 0.9/0.999) on
+ * sum_s w_s (exp(f_s) a_s - t_s)^2 / m from the initial weights in w_inout
+ * (host f32[193], overwritten with the result).  loss_out (host f64[epochs] or
+ * NULL) receives the loss before each step.  The trained weights are also set
+ * on the context. */
+int ofks_lp_train(ofks_ctx *ctx, const float *dev_samples, int64_t m, int32_t epochs, float lr,
+                  float *w_inout, float *norm_out, double *loss_out);
+
+/* Loss and gradient sums (host f64 scalar and f64[193]) of the training
+ * objective over m device samples for the given weights (parity checks). */
+int ofks_lp_loss_grad(ofks_ctx *ctx, const float *dev_samples, int64_t m, const float *host_w,
+                      const float *host_norm, double *loss, double *grad);
+
+/* P = exp(f) J G for a device block G (f64 n x p) with shifts lam (host
+ * f64[p]), using the context's weights (parity checks). */
+int ofks_lp_apply(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, double *P);
+
 /* ---- timing ------------------------------------------------------------ */
 
 /* Kernel timers (HIP events on the context stream).  enable = 1 starts
@@ -196,7 +237,7 @@ int ofks_build_hamiltonian(ofks_ctx *ctx, int32_t p, const double *X, double *rh
 int ofks_timing(ofks_ctx *ctx, int32_t enable);
 /* Totals for a kernel class: name is one of "spmm_dual", "spmm_shift",
  * "gram", "update_a", "update_b", "pcg_xr", "pcg_dir", "density", "poisson",
- * "assemble_h", "bbdot", "mlp".  ms = summed duration, launches = count. */
+ * "assemble_h", "bbdot", "mlp", "mlp_train".  ms = summed duration, launches = count. */
 int ofks_timer_get(ofks_ctx *ctx, const char *name, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

@@ -44,11 +44,14 @@ class Params:
     beta: float = 1.0
     tol: float = 1e-8
     max_iter: int = 1000
-    precond: str = "none"          # "none" | "paper"
+    precond: str = "none"          # "none" | "paper" | "learned"
     pcg_iters: int = 10
     eta0: float = 0.0              # > 0: fixed first eta
     step_rule: str = "bb2"         # "bb2" | "bb1" | "abb1" | "abb2" | "fixed"
     precond_lambda: str = "lambda2"
+    lp_weights: object = None      # learned form: (W[193], norm[8])
+    fallback_window: int = 5
+    fallback_hold: int = 20
 
 
 @dataclasses.dataclass
@@ -133,11 +136,17 @@ def pcg_shifted(prob, G: np.ndarray, lam: np.ndarray, iters: int) -> np.ndarray:
     return x
 
 
-def precondition(prob, G, lam_diag, params: Params):
-    if params.precond == "none":
+def precondition(prob, G, lam_diag, params: Params, kind: str = None):
+    kind = kind or params.precond
+    if kind == "none":
         return G
-    if params.precond != "paper":
-        raise ValueError(params.precond)
+    if kind == "learned":
+        from . import mlp
+        W, norm = params.lp_weights
+        lhd = prob.diag(prob.Lhval)
+        return mlp.apply(W, norm, lhd, prob.diag(prob.Bval), prob.diag(prob.Hval), lam_diag, G)
+    if kind != "paper":
+        raise ValueError(kind)
     neg = lam_diag < 0
     P = G.copy()
     if np.any(neg):
@@ -175,6 +184,9 @@ def pcal(prob, X0: np.ndarray, params: Params,
     Xprev = Pprev = None
     eta = eta0 = None
     kkt0 = None
+    ehist: List[float] = []
+    hold = 0
+    last_kind = None
     for k in range(params.max_iter + 1):
         prob.set_x(X)
         HX = prob.hx(X)
@@ -195,12 +207,27 @@ def pcal(prob, X0: np.ndarray, params: Params,
         Lam = multiplier(S, L0, params.beta)
         G = HX + BX @ (params.beta * (S - I) - Lam)
         lam_diag = np.diag(Lam) if params.precond_lambda == "lambda2" else np.diag(L0)
-        P = precondition(prob, G, lam_diag.copy(), params)
+        kind = params.precond
+        if params.precond == "learned":
+            # fall back to the paper preconditioner for fallback_hold steps when
+            # E^k exceeds the minimum of the previous fallback_window energies
+            use_learned = hold == 0
+            if use_learned and ehist and E > min(ehist) + 1e-12 * abs(E):
+                hold = max(1, params.fallback_hold)
+                use_learned = False
+            ehist = (ehist + [E])[-max(1, params.fallback_window):]
+            kind = "learned" if use_learned else "paper"
+            if hold > 0 and not use_learned:
+                hold -= 1
+        P = precondition(prob, G, lam_diag.copy(), params, kind)
         if k == 0:
             eta0 = params.eta0 if params.eta0 > 0 else float(np.linalg.norm(P) / np.linalg.norm(X))
             eta = eta0
+        elif kind != last_kind:
+            pass                                   # BB history restarts; eta carries over
         else:
             eta = bb_eta(params.step_rule, k, X - Xprev, P - Pprev, eta, eta0)
+        last_kind = kind
         Xt = X - P / eta
         dn = np.sqrt(np.einsum("ij,ij->j", Xt, prob.bx(Xt)))
         Xprev, Pprev = X, P

@@ -5,7 +5,8 @@
 //  k_colsum      fixed-order reduction of per-block partials.
 //  k_rowgemm     [G | R] = (BX D^-1) [C | C'] + (HX D^-1) with the update
 //                epilogues (gradient of L_beta, residual norm for kkt, the
-//                start of the preconditioner's CG), or a plain Y = X M.
+//                start of the preconditioner's CG or the column norms of G
+//                for the learned form), or a plain Y = X M.
 //  k_pcg_xr      x += alpha d, r -= alpha q, <r, J r>   (inner CG step)
 //  k_pcg_dir     d = J r + beta d
 //  k_pcg_scalars alpha / beta per column on the device
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void k_colsum(int64_t nb, int64_t m_total,
 // for c in [0, N).  Tile: 16*MT rows x 16*NT columns; thread (ty, tx) owns
 // rows r0 + ty + 16 i, columns c0 + tx + 16 j.  Persistent over row tiles.
 // ---------------------------------------------------------------------------
-enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2 };
+enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2, EPI_GRAD_NORM = 3 };
 
 struct GradArgs {
     const void *HX;       // n x p, unnormalized (scaled by dinv here)
@@ -194,6 +195,9 @@ __global__ __launch_bounds__(256) void k_rowgemm(int64_t n, int p, int N, const 
                         r2 += (double)v * (double)v;
                     } else if (EPI == EPI_GRAD) {
                         ((T *)ga.P)[r * p + c] = v;
+                    } else if (EPI == EPI_GRAD_NORM) {
+                        ((T *)ga.P)[r * p + c] = v;
+                        rz[j] += (double)v * (double)v;
                     } else {  // EPI_GRAD_PCG
                         if (ga.active[c]) {
                             const T jinv = T(1) / (T(ga.lhd[r]) - lamv[c] * T(ga.bd[r]));
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(256) void k_rowgemm(int64_t n, int p, int N, const 
     }
     if (threadIdx.x == 0) part[0] = red[0];
     __syncthreads();
-    if (EPI == EPI_GRAD_PCG) {
+    if (EPI == EPI_GRAD_PCG || EPI == EPI_GRAD_NORM) {
         for (int c = threadIdx.x; c < p; c += 256)
             if (c < c0 || c >= c0 + TC) part[1 + c] = 0.0;
 #pragma unroll
@@ -631,6 +635,7 @@ hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int g
     if (nt == NT_ && mt == MT_) {                                                             \
         if (epi == EPI_PLAIN) hipLaunchKernelGGL((k_rowgemm<T, MT_, NT_, EPI_PLAIN>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
         else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_rowgemm<T, MT_, NT_, EPI_GRAD>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else if (epi == EPI_GRAD_NORM) hipLaunchKernelGGL((k_rowgemm<T, MT_, NT_, EPI_GRAD_NORM>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
         else hipLaunchKernelGGL((k_rowgemm<T, MT_, NT_, EPI_GRAD_PCG>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
         return hipGetLastError();                                                             \
     }

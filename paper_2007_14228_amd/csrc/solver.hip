@@ -53,7 +53,9 @@ struct GradArgs {
     const uint8_t *active;
     double *part;
 };
-enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2 };
+enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2, EPI_GRAD_NORM = 3 };
+constexpr int LP_NPAR = 193;
+constexpr int LP_SAMPLE = 8;
 struct GramPlan {
     int mt, nt, gx, gy;
     int64_t splits, rows_per_split;
@@ -108,6 +110,18 @@ hipError_t launch_split_pairs(hipStream_t, int64_t, const double2 *, double *, d
 hipError_t launch_make_pairs(hipStream_t, int64_t, const double *, const double *, double2 *);
 hipError_t launch_diag(hipStream_t, int64_t, const int64_t *, const int32_t *, const double2 *, double *, double *,
                        int32_t *);
+// (k_mlp.hip)
+template <typename T>
+hipError_t launch_lp_apply(hipStream_t, int64_t, int, T *, const double *, const double *, const double *, const T *,
+                           const uint8_t *, const double *, const float *, const float *);
+template <typename T>
+hipError_t launch_lp_sample(hipStream_t, int64_t, int, int64_t, int64_t, int64_t, const T *, const T *,
+                            const double *, const double *, const double *, const T *, const uint8_t *,
+                            const double *, const double *, float *);
+hipError_t launch_lp_grad(hipStream_t, int, int64_t, const float *, const float *, const float *, double *);
+hipError_t launch_lp_adam(hipStream_t, const double *, double, float *, float *, float *, float, float, float, float,
+                          int);
+hipError_t launch_lp_stats(hipStream_t, int, int64_t, const float *, double *);
 // (k_density.hip)
 template <typename T>
 hipError_t launch_density_xc(hipStream_t, int, int64_t, int, const int32_t *, const int32_t *, const double *,
@@ -203,8 +217,15 @@ struct ofks_ctx {
     std::vector<double> dinv_h, S, L0;
     double last_kkt = NAN, last_fea = NAN, last_rel = NAN, last_energy = NAN;
     bool dinv_from_scf = false;
-    // learned form bookkeeping
-    std::vector<double> ehist;
+    // learned form
+    std::vector<double> ehist;   // recent energies (fallback rule)
+    float *lp_W = nullptr, *lp_norm = nullptr;
+    bool lp_ready = false;
+    int lp_hold = 0;             // iterations left on the paper preconditioner after a fallback
+    int last_kind = -1;          // preconditioner of the previous step (BB restarts on a change)
+    double *g2 = nullptr, *tw = nullptr;
+    float *lp_buf = nullptr;     // training-sample collection
+    int64_t lp_cap = 0, lp_count = 0, lp_stride = 0;
 
     // timing
     bool timing = false;
@@ -642,28 +663,62 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     c->S = S;
     c->L0 = L0;
 
-    const bool pcg = c->prm.precond == OFKS_PRECOND_PAPER;
+    // energy of X^k (needed before the preconditioner choice in the learned form)
+    const bool learned_form = c->prm.precond == OFKS_PRECOND_LEARNED;
+    double energy = NAN;
+    const int ee = learned_form ? 1 : std::max(1, c->prm.energy_every);
+    if (scf) {
+        double trl = 0.0;
+        for (int i = 0; i < p; ++i) trl += L0[i * p + i];
+        energy = c->prm.occupation * trl - c->scf_parts[3] - c->scf_parts[2] + c->scf_parts[1] + c->Enuc;
+    } else if (c->k % ee == 0) {
+        double tr;
+        if (dense::trace_sinv_a(S, L0, p, tr)) energy = tr;
+    }
+    // learned form: fall back to the paper preconditioner for fallback_hold
+    // iterations when the energy rises above the minimum of the last
+    // fallback_window iterates
+    bool use_learned = learned_form && c->lp_hold == 0;
+    int fell_back = 0;
+    if (learned_form && std::isfinite(energy)) {
+        if (use_learned && !c->ehist.empty()) {
+            const double mn = *std::min_element(c->ehist.begin(), c->ehist.end());
+            if (energy > mn + 1e-12 * std::fabs(energy)) {
+                c->lp_hold = std::max(1, c->prm.fallback_hold);
+                use_learned = false;
+                fell_back = 1;
+            }
+        }
+        c->ehist.push_back(energy);
+        const size_t W = (size_t)std::max(1, c->prm.fallback_window);
+        while (c->ehist.size() > W) c->ehist.erase(c->ehist.begin());
+    }
+    const bool use_paper = c->prm.precond == OFKS_PRECOND_PAPER || (learned_form && !use_learned);
+    const int kind = use_learned ? OFKS_PRECOND_LEARNED : (use_paper ? OFKS_PRECOND_PAPER : OFKS_PRECOND_NONE);
+
     std::vector<double> shift(p, 0.0);
-    std::vector<uint8_t> act(p, 0);
+    std::vector<uint8_t> neg(p, 0);
     bool any_active = false;
     for (int i = 0; i < p; ++i) {
         const double li = c->prm.precond_lambda == 0 ? lam_diag[i] : L0[i * p + i];
         shift[i] = li;
-        act[i] = (pcg && li < 0.0) ? 1 : 0;
-        any_active |= act[i] != 0;
+        neg[i] = li < 0.0 ? 1 : 0;
+        any_active |= use_paper && neg[i];
     }
+    std::vector<uint8_t> act(p, 0);
+    for (int i = 0; i < p; ++i) act[i] = (use_paper && neg[i]) ? 1 : 0;
     if (!scf) CHK(upload<T>(c, B.dinv, dn));
     CHK(upload<T>(c, B.CC, CC));
     CHK(upload<T>(c, B.lam, shift));
-    CHK(upload_bytes(c, c->active, act.data(), p));
+    CHK(upload_bytes(c, c->active, use_learned ? neg.data() : act.data(), p));
 
-    // G, R (kkt) and the start of the CG
+    // G, R (kkt) and the start of the CG (paper) or the column norms of G (learned)
     int gx = 0;
-    const int epi = any_active ? EPI_GRAD_PCG : EPI_GRAD;
+    const int epi = (use_paper && any_active) ? EPI_GRAD_PCG : (use_learned ? EPI_GRAD_NORM : EPI_GRAD);
+    const int tc = rowgemm_tile_cols(2 * p);
+    const int gy = (2 * p + tc - 1) / tc;
+    CHK(ensure_part(c, (size_t)c->gemm_rows * gy * (1 + p)));
     {
-        const int tc = rowgemm_tile_cols(2 * p);
-        const int gy = (2 * p + tc - 1) / tc;
-        CHK(ensure_part(c, (size_t)c->gemm_rows * gy * (1 + p)));
         // built after the partial buffer is final: it carries that pointer
         GradArgs ga{B.HX, B.P, B.R, B.D, c->lhd, c->bd, B.lam, c->active, c->part};
         {
@@ -678,16 +733,6 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     const double kkt = std::sqrt(std::max(0.0, r2[0]));
     if (c->kkt0 < 0) c->kkt0 = kkt;
     const double rel = (kkt + fea) / c->kkt0;
-    double energy = NAN;
-    const int ee = std::max(1, c->prm.energy_every);
-    if (scf) {
-        double trl = 0.0;
-        for (int i = 0; i < p; ++i) trl += L0[i * p + i];
-        energy = c->prm.occupation * trl - c->scf_parts[3] - c->scf_parts[2] + c->scf_parts[1] + c->Enuc;
-    } else if (c->k % ee == 0) {
-        double tr;
-        if (dense::trace_sinv_a(S, L0, p, tr)) energy = tr;
-    }
     c->last_kkt = kkt;
     c->last_fea = fea;
     c->last_rel = rel;
@@ -700,8 +745,8 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         st->energy = energy;
         st->eta = c->eta;
         st->precision = std::is_same<T, double>::value ? OFKS_F64 : OFKS_F32;
-        st->precond_used = c->prm.precond;
-        st->fell_back = 0;
+        st->precond_used = kind;
+        st->fell_back = fell_back;
     }
     if (!std::isfinite(rel))
         return fail(c, OFKS_ENONFINITE, "non-finite residual at k=%d: kkt=%g fea=%g kkt0=%g", c->k, kkt, fea,
@@ -711,10 +756,24 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return OFKS_OK;
     }
+    if (c->lp_hold > 0 && !use_learned) c->lp_hold -= 1;
+    if (kind != c->last_kind) c->have_prev = false;   // BB restarts, eta carries over
+    c->last_kind = kind;
+
+    // training samples: keep G (and its column norms) before the CG overwrites it
+    const bool collect = c->lp_buf && use_paper && any_active && c->lp_count < c->lp_cap;
+    if (collect) {
+        GradArgs gn{B.HX, B.P, B.R, B.D, c->lhd, c->bd, B.lam, c->active, c->part};
+        HIPCHK(launch_rowgemm<T>(c->stream, EPI_GRAD_NORM, n, p, 2 * p, c->gemm_rows, B.BX, B.dinv, B.CC, nullptr, gn,
+                                 &gx));
+        HIPCHK(launch_colsum(c->stream, (int64_t)gx * gy, 1 + p, c->part, c->red));
+        HIPCHK(hipMemcpyAsync(c->g2, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(B.BX, B.P, (size_t)n * p * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    }
 
     // preconditioner: columnwise Jacobi-PCG from zero, fixed iteration count
-    if (any_active) {
-        HIPCHK(hipMemcpyAsync(c->rz, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (use_paper && any_active) {
+        CHK(upload_bytes(c, c->rz, r2.data() + 1, p * sizeof(double)));
         CHK(ensure_part(c, (size_t)c->grid * p));
         for (int it = 0; it < c->prm.pcg_iters; ++it) {
             int used = 0;
@@ -737,6 +796,30 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
                 HIPCHK(launch_pcg_dir<T>(c->stream, n, p, B.beta, c->active, c->lhd, c->bd, B.lam, B.R, B.D));
             }
         }
+    }
+    if (collect) {
+        // t = T^-1 g (this step's P), weights 1 / mean_i t_il^2, every lp_stride-th row
+        std::vector<double> pp;
+        CHK(coldot<T>(c, B.P, B.P, pp));
+        std::vector<double> w(p);
+        for (int i = 0; i < p; ++i) w[i] = pp[i] > 0 ? (double)n / pp[i] : 0.0;
+        CHK(upload<double>(c, c->tw, w));
+        const int64_t stride = std::max<int64_t>(1, c->lp_stride);
+        const int64_t offset = (c->k * 7919) % stride;
+        int64_t rows = (n - offset + stride - 1) / stride;
+        rows = std::min<int64_t>(rows, (c->lp_cap - c->lp_count) / p);
+        if (rows > 0) {
+            HIPCHK(launch_lp_sample<T>(c->stream, n, p, offset, stride, rows, B.BX, B.P, c->lhd, c->bd, c->hd, B.lam,
+                                       c->active, c->g2, c->tw, c->lp_buf + c->lp_count * LP_SAMPLE));
+            c->lp_count += rows * p;
+        }
+    }
+    if (use_learned) {
+        if (!c->lp_ready) return fail(c, OFKS_ESTATE, "learned preconditioner: no weights (ofks_lp_set_weights)");
+        HIPCHK(hipMemcpyAsync(c->g2, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        Scope sc(c, "mlp");
+        HIPCHK(launch_lp_apply<T>(c->stream, n, p, B.P, c->lhd, c->bd, c->hd, B.lam, c->active, c->g2, c->lp_W,
+                                  c->lp_norm));
     }
 
     // BB step
@@ -1144,7 +1227,8 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
     if (prm->scf && !c->assembled) return fail(c, OFKS_ESTATE, "set_params: SCF needs an assembled mesh");
     if (prm->precond == OFKS_PRECOND_PAPER && c->has_system && !c->has_lhalf)
         return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs L/2 (csr_load without Lhalf)");
-    if (prm->precond == OFKS_PRECOND_LEARNED) return fail(c, OFKS_EINVAL, "set_params: learned form not built");
+    if (prm->precond == OFKS_PRECOND_LEARNED && c->has_system && !c->has_lhalf)
+        return fail(c, OFKS_EINVAL, "set_params: the learned preconditioner needs L/2 (its fallback is the paper's)");
     c->prm = *prm;
     if (c->prm.energy_every < 1) c->prm.energy_every = 1;
     c->has_params = true;
@@ -1163,8 +1247,12 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     dfree(c, c->rz);
     c->p = p;
     c->prec = c->prm.precision;
+    dfree(c, c->g2);
+    dfree(c, c->tw);
     CHK(dalloc(c, &c->active, p));
     CHK(dalloc(c, &c->rz, p));
+    CHK(dalloc(c, &c->g2, p));
+    CHK(dalloc(c, &c->tw, p));
     CHK(ensure_part(c, partials_needed(c, p)));
     CHK(alloc_blocks<double>(c));
     Blocks<double> &B = c->b64;
@@ -1206,6 +1294,8 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     c->done = false;
     c->has_x = true;
     c->ehist.clear();
+    c->lp_hold = 0;
+    c->last_kind = -1;
     return sync(c);
 }
 
@@ -1442,6 +1532,145 @@ int ofks_build_hamiltonian(ofks_ctx *c, int32_t p, const double *X, double *rho_
     if (parts)
         for (int i = 0; i < 4; ++i) parts[i] = c->scf_parts[i];
     return sync(c);
+}
+
+// ---- learned preconditioner ------------------------------------------------
+
+int ofks_lp_set_weights(ofks_ctx *c, const float *w, const float *norm) {
+    if (!c) return OFKS_EINVAL;
+    if (!w || !norm) return fail(c, OFKS_EINVAL, "lp_set_weights: null pointer");
+    for (int i = 0; i < 4; ++i)
+        if (!(norm[4 + i] > 0.0f)) return fail(c, OFKS_EINVAL, "lp_set_weights: feature scales must be > 0");
+    if (!c->lp_W) {
+        CHK(dalloc(c, &c->lp_W, LP_NPAR));
+        CHK(dalloc(c, &c->lp_norm, 8));
+    }
+    HIPCHK(hipMemcpyAsync(c->lp_W, w, LP_NPAR * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->lp_norm, norm, 8 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->lp_ready = true;
+    return OFKS_OK;
+}
+
+int ofks_lp_collect(ofks_ctx *c, int64_t row_stride, float *dev_buf, int64_t cap) {
+    if (!c) return OFKS_EINVAL;
+    if (dev_buf && (cap <= 0 || row_stride <= 0)) return fail(c, OFKS_EINVAL, "lp_collect: bad capacity or stride");
+    c->lp_buf = dev_buf;
+    c->lp_cap = dev_buf ? cap : 0;
+    c->lp_stride = row_stride;
+    if (dev_buf) c->lp_count = 0;   // stopping keeps the count readable
+    return OFKS_OK;
+}
+
+int ofks_lp_collected(ofks_ctx *c, int64_t *count) {
+    if (!c || !count) return OFKS_EINVAL;
+    *count = c->lp_count;
+    return OFKS_OK;
+}
+
+namespace {
+// sums of per-block partials of the loss and its gradient for the current weights
+int lp_loss_grad_dev(ofks_ctx *c, const float *S, int64_t m, int grid) {
+    HIPCHK(launch_lp_grad(c->stream, grid, m, S, c->lp_W, c->lp_norm, c->part));
+    HIPCHK(launch_colsum(c->stream, grid, LP_NPAR + 1, c->part, c->red));
+    return OFKS_OK;
+}
+}  // namespace
+
+int ofks_lp_loss_grad(ofks_ctx *c, const float *dev_samples, int64_t m, const float *w, const float *norm,
+                      double *loss, double *grad) {
+    if (!c) return OFKS_EINVAL;
+    if (!dev_samples || m <= 0 || !w || !norm || !loss || !grad) return fail(c, OFKS_EINVAL, "lp_loss_grad: bad arguments");
+    CHK(ofks_lp_set_weights(c, w, norm));
+    if (!c->red) CHK(dalloc(c, &c->red, 2 * 1024 * 1024 + 64));
+    const int grid = 512;
+    CHK(ensure_part(c, (size_t)grid * (LP_NPAR + 1)));
+    CHK(lp_loss_grad_dev(c, dev_samples, m, grid));
+    std::vector<double> out;
+    CHK(download(c, out, c->red, LP_NPAR + 1));
+    for (int k = 0; k < LP_NPAR; ++k) grad[k] = out[k];
+    *loss = out[LP_NPAR];
+    return OFKS_OK;
+}
+
+int ofks_lp_train(ofks_ctx *c, const float *dev_samples, int64_t m, int32_t epochs, float lr, float *w_inout,
+                  float *norm_out, double *loss_out) {
+    if (!c) return OFKS_EINVAL;
+    if (!dev_samples || m <= 0 || epochs < 0 || !(lr > 0.0f) || !w_inout || !norm_out)
+        return fail(c, OFKS_EINVAL, "lp_train: bad arguments");
+    if (!c->red) CHK(dalloc(c, &c->red, 2 * 1024 * 1024 + 64));
+    const int grid = 512;
+    CHK(ensure_part(c, (size_t)grid * (LP_NPAR + 1)));
+    // feature standardization from the samples
+    HIPCHK(launch_lp_stats(c->stream, grid, m, dev_samples, c->part));
+    HIPCHK(launch_colsum(c->stream, grid, 8, c->part, c->red));
+    std::vector<double> st;
+    CHK(download(c, st, c->red, 8));
+    float norm[8];
+    for (int j = 0; j < 4; ++j) {
+        const double mu = st[j] / (double)m;
+        const double var = std::max(0.0, st[4 + j] / (double)m - mu * mu);
+        norm[j] = (float)mu;
+        norm[4 + j] = (float)std::max(1e-6, std::sqrt(var));
+    }
+    CHK(ofks_lp_set_weights(c, w_inout, norm));
+    float *m1 = nullptr, *m2 = nullptr;
+    double *losses = nullptr;
+    CHK(dalloc(c, &m1, LP_NPAR));
+    CHK(dalloc(c, &m2, LP_NPAR));
+    CHK(dalloc(c, &losses, std::max(epochs, 1)));
+    HIPCHK(hipMemsetAsync(m1, 0, LP_NPAR * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(m2, 0, LP_NPAR * sizeof(float), c->stream));
+    for (int t = 1; t <= epochs; ++t) {
+        {
+            Scope sc(c, "mlp_train");
+            CHK(lp_loss_grad_dev(c, dev_samples, m, grid));
+            HIPCHK(launch_lp_adam(c->stream, c->red, 1.0 / (double)m, c->lp_W, m1, m2, lr, 0.9f, 0.999f, 1e-8f, t));
+        }
+        HIPCHK(hipMemcpyAsync(losses + (t - 1), c->red + LP_NPAR, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(hipMemcpyAsync(w_inout, c->lp_W, LP_NPAR * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (loss_out && epochs > 0)
+        HIPCHK(hipMemcpyAsync(loss_out, losses, epochs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    for (int j = 0; j < 8; ++j) norm_out[j] = norm[j];
+    if (loss_out)
+        for (int t = 0; t < epochs; ++t) loss_out[t] /= (double)m;
+    dfree(c, m1);
+    dfree(c, m2);
+    dfree(c, losses);
+    return OFKS_OK;
+}
+
+int ofks_lp_apply(ofks_ctx *c, int32_t p, const double *lam, const double *G, double *P) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "lp_apply: needs an assembled system");
+    if (!c->lp_ready) return fail(c, OFKS_ESTATE, "lp_apply: no weights");
+    if (p <= 0 || p > 1024 || !lam || !G || !P) return fail(c, OFKS_EINVAL, "lp_apply: bad arguments");
+    const int keep = c->p;
+    c->p = p;
+    double *lamd = nullptr, *g2 = nullptr;
+    uint8_t *neg = nullptr;
+    CHK(dalloc(c, &lamd, p));
+    CHK(dalloc(c, &g2, p));
+    CHK(dalloc(c, &neg, p));
+    std::vector<double> lv(lam, lam + p);
+    std::vector<uint8_t> nh(p);
+    for (int i = 0; i < p; ++i) nh[i] = lam[i] < 0.0 ? 1 : 0;
+    CHK(upload<double>(c, lamd, lv));
+    CHK(upload_bytes(c, neg, nh.data(), p));
+    std::vector<double> gg;
+    int rc = coldot<double>(c, G, G, gg);
+    if (rc >= 0) rc = upload<double>(c, g2, gg);
+    c->p = keep;
+    CHK(rc);
+    HIPCHK(hipMemcpyAsync(P, G, (size_t)c->n * p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(launch_lp_apply<double>(c->stream, c->n, p, P, c->lhd, c->bd, c->hd, lamd, neg, g2, c->lp_W, c->lp_norm));
+    CHK(sync(c));
+    dfree(c, lamd);
+    dfree(c, g2);
+    dfree(c, neg);
+    return OFKS_OK;
 }
 
 int ofks_timing(ofks_ctx *c, int32_t enable) {

@@ -252,6 +252,56 @@ class Solver:
                                                     _dev_ptr(eps), _dev_ptr(vxc), _dev_ptr(U), _np_ptr(parts)))
         return dict(rho=rho, eps=eps, vxc=vxc, U=U, parts=parts)
 
+    # -- learned preconditioner -------------------------------------------------
+    def lp_set_weights(self, w: np.ndarray, norm: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        if w.shape != (193,) or norm.shape != (8,):
+            raise ValueError("weights must be 193 floats and norm 8 floats")
+        self._check(self.lib.ofks_lp_set_weights(self.h, _np_ptr(w), _np_ptr(norm)))
+
+    def lp_collect(self, buf, row_stride: int):
+        """buf: device float32 tensor [cap, 8] (or None to stop)."""
+        if buf is None:
+            self._check(self.lib.ofks_lp_collect(self.h, 0, ctypes.c_void_p(None), 0))
+            return
+        if buf.dim() != 2 or int(buf.shape[1]) != 8:
+            raise ValueError("sample buffer must be [cap, 8]")
+        self._check(self.lib.ofks_lp_collect(self.h, int(row_stride), _dev_ptr(buf, "float32"), int(buf.shape[0])))
+
+    def lp_collected(self) -> int:
+        n = ctypes.c_int64()
+        self._check(self.lib.ofks_lp_collected(self.h, ctypes.byref(n)))
+        return int(n.value)
+
+    def lp_train(self, samples, epochs: int, lr: float, w0: np.ndarray):
+        m = int(samples.shape[0])
+        w = np.ascontiguousarray(w0, dtype=np.float32).copy()
+        norm = np.empty(8, dtype=np.float32)
+        loss = np.empty(max(epochs, 1))
+        self._check(self.lib.ofks_lp_train(self.h, _dev_ptr(samples, "float32"), m, int(epochs), float(lr),
+                                           _np_ptr(w), _np_ptr(norm), _np_ptr(loss)))
+        return w, norm, loss[:epochs]
+
+    def lp_loss_grad(self, samples, w: np.ndarray, norm: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        loss = ctypes.c_double()
+        grad = np.empty(193)
+        self._check(self.lib.ofks_lp_loss_grad(self.h, _dev_ptr(samples, "float32"), int(samples.shape[0]),
+                                               _np_ptr(w), _np_ptr(norm), ctypes.byref(loss), _np_ptr(grad)))
+        return loss.value, grad
+
+    def lp_apply(self, lam: np.ndarray, G):
+        import torch
+        _check_block(G, self.n)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (int(G.shape[1]),):
+            raise ValueError("lam must have one entry per column")
+        P = torch.empty_like(G)
+        self._check(self.lib.ofks_lp_apply(self.h, int(G.shape[1]), _np_ptr(lam), _dev_ptr(G), _dev_ptr(P)))
+        return P
+
     # -- timing ----------------------------------------------------------------
     def timing(self, enable: bool = True):
         self._check(self.lib.ofks_timing(self.h, 1 if enable else 0))

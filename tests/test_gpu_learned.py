@@ -1,0 +1,175 @@
+"""GPU parity of the learned preconditioner's kernels against the oracle.
+
+Tolerances: the network runs in FP32 on the device and FP64 in the oracle,
+so results agree to ~1e-6 relative; tests use 2e-5."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import fem, mlp, pcal
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = wl.make_workload("c1")
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    return w, d, prob
+
+
+def _weights(seed=3):
+    W = mlp.init_weights(seed)
+    W[5 * mlp.H:] = np.random.default_rng(seed + 1).standard_normal(mlp.H + 1) * 0.2
+    return W.astype(np.float32).astype(np.float64)
+
+
+def _samples(m, seed):
+    rng = np.random.default_rng(seed)
+    S = np.zeros((m, 8), dtype=np.float32)
+    S[:, :4] = rng.standard_normal((m, 4)) * [1.0, 2.0, 3.0, 0.5] + [1.0, -5.0, -2.0, 0.0]
+    S[:, 4] = rng.standard_normal(m)
+    S[:, 5] = S[:, 4] * np.exp(0.3 * rng.standard_normal(m))
+    S[:, 6] = rng.uniform(0.5, 2.0, m)
+    return S
+
+
+def test_loss_and_gradient_match_the_oracle():
+    from paper_2007_14228_amd import Solver
+    print("[gpu] lp loss/grad", flush=True)
+    S = _samples(200_000, 5)
+    W = _weights()
+    norm = np.array([1.0, -5.0, -2.0, 0.0, 1.0, 2.0, 3.0, 0.5], dtype=np.float32)
+    s = Solver()
+    loss, g = s.lp_loss_grad(_dev(S), W, norm)
+    ref_loss, ref_g = mlp.loss_grad(W, norm.astype(np.float64), S.astype(np.float64))
+    assert abs(loss - ref_loss) <= 2e-5 * ref_loss
+    assert np.linalg.norm(g - ref_g) <= 2e-5 * np.linalg.norm(ref_g)
+
+
+def test_apply_matches_the_oracle(c1):
+    from paper_2007_14228_amd import Solver
+    print("[gpu] lp apply", flush=True)
+    w, d, prob = c1
+    s = Solver()
+    s.load_workload(w)
+    W = _weights(7)
+    norm = np.array([-1.0, -2.0, -1.0, 0.0, 1.0, 1.5, 2.0, 1.0], dtype=np.float32)
+    s.lp_set_weights(W, norm)
+    G = np.random.default_rng(2).standard_normal((d.n, 5))
+    lam = np.array([-0.7, 0.2, -2.0, -0.1, 0.0])
+    P = s.lp_apply(lam, _dev(G)).cpu().numpy()
+    ref = mlp.apply(W, norm.astype(np.float64), prob.diag(0.5 * d.L), prob.diag(d.B), prob.diag(d.H), lam, G)
+    assert np.abs(P - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_training_lowers_the_loss_and_reports_it_consistently():
+    from paper_2007_14228_amd import Solver
+    print("[gpu] lp train", flush=True)
+    S = _samples(100_000, 9)
+    # a target the network can represent: t = a exp(0.5 tanh(x0) - 0.3 x3)
+    S[:, 5] = S[:, 4] * np.exp(0.5 * np.tanh(S[:, 0] - 1.0) - 0.3 * S[:, 3] / 0.5)
+    s = Solver()
+    W0 = mlp.init_weights(1).astype(np.float32)
+    W, norm, losses = s.lp_train(_dev(S), 300, 1e-2, W0)
+    assert losses[-1] < 0.2 * losses[0]
+    # the reported loss of the final weights agrees with the oracle's definition
+    final, _ = mlp.loss_grad(W.astype(np.float64), norm.astype(np.float64), S.astype(np.float64))
+    loss, _ = s.lp_loss_grad(_dev(S), W, norm)
+    assert abs(loss - final) <= 2e-5 * final
+    assert np.all(norm[4:] > 0)
+    assert np.allclose(norm[:4], S[:, :4].astype(np.float64).mean(axis=0), rtol=1e-4, atol=1e-5)
+
+
+def test_learned_form_follows_the_oracle_then_converges(c1):
+    """First iterations of the learned form against the oracle's (FP32 network:
+    1e-5), then convergence to the dense eigenvalues."""
+    from paper_2007_14228_amd import Solver
+    print("[gpu] lp pcal", flush=True)
+    w, d, prob = c1
+    W = _weights(11)
+    norm = np.array([-1.0, -2.0, -1.0, 0.0, 1.0, 1.5, 2.0, 1.0], dtype=np.float32)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=4, precond="learned",
+                                              lp_weights=(W, norm.astype(np.float64))))
+    s = Solver()
+    s.load_workload(w)
+    s.lp_set_weights(W, norm)
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=4, precond="learned")
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, _, _ = s.step(5)
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-5 * b.kkt
+    s.set_params(beta=w.beta, tol=1e-10, max_iter=3000, precond="learned")
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, done, _ = s.step(3000)
+    assert done and st[-1]["rel"] < 1e-10
+    ref = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p]
+    assert abs(st[-1]["energy"] - sum(ref)) < 1e-9 * abs(sum(ref))
+
+
+def test_poisoned_network_falls_back_and_still_converges(c1):
+    """Fallback forced from the host: an output bias of 3 makes every learned
+    step 20x too long; the energy rises, the paper preconditioner takes over,
+    and the run converges to the same energy."""
+    from paper_2007_14228_amd import Solver
+    print("[gpu] lp fallback", flush=True)
+    w, d, prob = c1
+    W = mlp.init_weights(0)
+    W[-1] = 3.0
+    norm = np.array([0, 0, 0, 0, 1, 1, 1, 1.0], dtype=np.float32)
+    s = Solver()
+    s.load_workload(w)
+    s.lp_set_weights(W, norm)
+    s.set_params(beta=w.beta, tol=1e-9, max_iter=3000, precond="learned", fallback_window=5, fallback_hold=20)
+    s.set_x0(_dev(wl.random_block(0, d.n, w.p)), orthonormalize=True)
+    st, done, _ = s.step(3000)
+    assert done and st[-1]["rel"] < 1e-9
+    assert sum(x["fell_back"] for x in st) >= 1
+    assert any(x["precond_used"] == 1 for x in st) and any(x["precond_used"] == 2 for x in st)
+    ref = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p]
+    assert abs(st[-1]["energy"] - sum(ref)) < 1e-8 * abs(sum(ref))
+
+
+def test_sample_collection_records_the_paper_preconditioner(c1):
+    """Samples hold the node features of the sampled rows, a = J g and the
+    paper preconditioner's output t for the same (row, column)."""
+    import torch
+    from paper_2007_14228_amd import Solver
+    print("[gpu] lp collect", flush=True)
+    w, d, prob = c1
+    s = Solver()
+    s.load_workload(w)
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=50, precond="paper", pcg_iters=10)
+    s.set_x0(_dev(wl.random_block(0, d.n, w.p)), orthonormalize=True)
+    stride = 37
+    buf = torch.zeros((10 * d.n, 8), dtype=torch.float32, device="cuda")
+    s.lp_collect(buf, stride)
+    # from a random start every Lambda_ll is positive (identity branch, no
+    # samples); columns take the T^-1 branch after about ten iterations
+    st, _, _ = s.step(30)
+    s.lp_collect(None, 0)
+    cnt = s.lp_collected()
+    assert cnt > 0 and cnt % w.p == 0
+    S = buf[:cnt].cpu().numpy()
+    lhd, bd, hd = prob.diag(0.5 * d.L), prob.diag(d.B), prob.diag(d.H)
+    node = mlp.node_features(lhd, bd, hd)
+    # every sample's node features are those of some row
+    # (matched on all three: on a uniform mesh the first two are the same for every row)
+    dist = sum(np.abs(node[None, :, j] - S[:, None, j]) / (1e-3 + np.abs(node[None, :, j])) for j in range(3))
+    rows = np.argmin(dist, axis=1)
+    assert np.allclose(S[:, :3], node[rows], rtol=2e-6, atol=2e-6)
+    assert np.all(np.isfinite(S)) and np.all(S[:, 6] > 0)
