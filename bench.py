@@ -41,7 +41,10 @@ def parse():
     ap.add_argument("--pcg-iters", type=int, default=10)
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-baseline", default="auto", choices=["auto", "skip"])
-    ap.add_argument("--max-iter", type=int, default=1000)
+    ap.add_argument("--max-iter", type=int, default=2000)
+    ap.add_argument("--weights", default=None, help="learned-preconditioner weights (JSON)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 2 GiB device copy (known bytes) for HBM counter calibration")
     return ap.parse_args()
 
 
@@ -77,10 +80,12 @@ def traffic_from_profiles(kernel, workload):
     return rec.get("bytes_per_launch") if h == rec.get("source_sha") else None
 
 
-def run_to_tol(torch, solver_cls, w, X0, tol, params):
-    s = solver_cls()
-    s.load_workload(w)
+def run_to_tol(torch, s, X0, tol, params, weights=None):
+    """Seconds from the first step to the first iterate with residual < tol
+    (setup excluded; X0 B-orthonormalized before the clock starts)."""
     s.set_params(tol=tol, **params)
+    if weights is not None:
+        s.lp_set_weights(*weights)
     s.set_x0(X0, orthonormalize=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -88,10 +93,15 @@ def run_to_tol(torch, solver_cls, w, X0, tol, params):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     last = stats[-1]
-    out = dict(seconds=dt, iterations=len(stats) - 1, rel=last["rel"], energy=last["energy"],
-               converged=bool(last["rel"] < tol), iter_per_s=(len(stats) - 1) / dt if dt > 0 else None)
-    s.close()
-    return out
+    iters = len(stats) - 1
+    kinds = [0, 0, 0]
+    for x in stats[:-1]:
+        kinds[x["precond_used"]] += 1
+    return dict(seconds=round(dt, 3), iterations=iters, rel=last["rel"], energy=float(s.energy()[4]),
+                converged=bool(last["rel"] < tol), iter_per_s=round(iters / dt, 3) if dt > 0 else None,
+                iterations_by_precond={"none": kinds[0], "paper": kinds[1], "learned": kinds[2]},
+                fallbacks=int(sum(x["fell_back"] for x in stats)),
+                fp32_iterations=int(sum(1 for x in stats[:-1] if x["precision"] == 1)))
 
 
 def cpu_baseline(w, X0_host, pcg_iters):
@@ -181,7 +191,6 @@ def main():
     roofline = dict(bound="hbm", kernel=kern, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kern, a.workload),
                     avg_launch_ms=round(avg, 4), algorithmic_bytes_per_launch=int(alg))
-    s.close()
 
     out = {
         "metric": METRIC,
@@ -203,17 +212,47 @@ def main():
         "kernel_ms": {k: round(v[0] / v[1], 4) for k, v in timers.items() if v[1]},
     }
 
+    if a.calibrate_copy:
+        # a plain copy of known size (2 GiB read + 2 GiB written) in the same
+        # process, so counter runs can scale FETCH_SIZE / WRITE_SIZE
+        src = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": int(src.numel() * 8), "write": int(dst.numel() * 8)}
+        del src, dst
+        torch.cuda.empty_cache()
+
     if not a.no_converge:
-        log("time to residual 1e-6: plain FP64")
-        plain = run_to_tol(torch, Solver, w, X0, 1e-6, params)
+        ttr = {}
+        log("time to residual 1e-6: plain FP64, paper preconditioner")
+        ttr["fp64_paper_precond"] = plain = run_to_tol(torch, s, X0, 1e-6, params)
         log(f"  {plain}")
-        log("time to residual 1e-6: mixed precision (FP32 blocks, FP64 p x p and refinement)")
+        log("time to residual 1e-6: mixed precision (FP32 blocks, FP64 p x p, FP64 refinement), paper preconditioner")
         mparams = dict(params, precision="f32", refine_tol=1e-5)
-        mixed = run_to_tol(torch, Solver, w, X0, 1e-6, mparams)
-        log(f"  {mixed}")
-        out["time_to_residual_1e-6"] = {"fp64_paper_precond": plain, "mixed_paper_precond": mixed}
-        if plain["converged"] and mixed["converged"]:
-            out["time_to_residual_1e-6"]["mixed_dE_vs_fp64_Ha"] = abs(mixed["energy"] - plain["energy"])
+        ttr["mixed_paper_precond"] = run_to_tol(torch, s, X0, 1e-6, mparams)
+        log(f"  {ttr['mixed_paper_precond']}")
+        from paper_2007_14228_amd import learned
+        wpath = a.weights or learned.DEFAULT_WEIGHTS
+        if os.path.exists(wpath):
+            Wl, norml, meta = learned.load(wpath)
+            log(f"time to residual 1e-6: mixed precision + learned preconditioner ({os.path.basename(wpath)})")
+            lparams = dict(mparams, precond="learned", energy_every=1)
+            ttr["mixed_learned_precond"] = run_to_tol(torch, s, X0, 1e-6, lparams, (Wl, norml))
+            ttr["mixed_learned_precond"]["weights"] = {"file": os.path.relpath(wpath, ROOT),
+                                                       **{k: meta[k] for k in ("seeds", "kind", "samples")
+                                                          if k in meta}}
+            log(f"  {ttr['mixed_learned_precond']}")
+        else:
+            ttr["mixed_learned_precond"] = {"error": f"no trained weights at {wpath}"}
+        for k, v in ttr.items():
+            if k != "fp64_paper_precond" and v.get("converged") and plain["converged"]:
+                v["dE_vs_fp64_Ha"] = abs(v["energy"] - plain["energy"])
+        ttr["speedup_vs_fp64_paper"] = {k: round(plain["seconds"] / v["seconds"], 3)
+                                        for k, v in ttr.items() if k != "fp64_paper_precond" and v.get("converged")}
+        out["time_to_residual_1e-6"] = ttr
+    s.close()
 
     if a.cpu_baseline == "auto":
         try:

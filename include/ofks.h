@@ -76,7 +76,9 @@ typedef struct {
     int32_t poisson_max_iter;
     int32_t fallback_window;/* learned form: W iterations of energy history */
     int32_t fallback_hold;  /* learned form: iterations on the paper preconditioner after a fallback */
-    int32_t reserved[5];
+    int32_t fallback_rule;  /* learned form: a fallback when E^k exceeds 0: the minimum, 1: the maximum
+                               of the previous fallback_window energies */
+    int32_t reserved[4];
 } ofks_params;
 
 typedef struct {

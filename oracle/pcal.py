@@ -52,6 +52,7 @@ class Params:
     lp_weights: object = None      # learned form: (W[193], norm[8])
     fallback_window: int = 5
     fallback_hold: int = 20
+    fallback_rule: str = "min"     # fall back when E^k exceeds the "min" or "max" of the window
 
 
 @dataclasses.dataclass
@@ -210,9 +211,10 @@ def pcal(prob, X0: np.ndarray, params: Params,
         kind = params.precond
         if params.precond == "learned":
             # fall back to the paper preconditioner for fallback_hold steps when
-            # E^k exceeds the minimum of the previous fallback_window energies
+            # E^k exceeds the minimum (or maximum) of the previous fallback_window energies
             use_learned = hold == 0
-            if use_learned and ehist and E > min(ehist) + 1e-12 * abs(E):
+            ref = (max if params.fallback_rule == "max" else min)(ehist) if ehist else None
+            if use_learned and ehist and E > ref + 1e-12 * abs(E):
                 hold = max(1, params.fallback_hold)
                 use_learned = False
             ehist = (ehist + [E])[-max(1, params.fallback_window):]

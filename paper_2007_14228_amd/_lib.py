@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
         ("poisson_max_iter", _c_int32),
         ("fallback_window", _c_int32),
         ("fallback_hold", _c_int32),
-        ("reserved", _c_int32 * 5),
+        ("fallback_rule", _c_int32),
+        ("reserved", _c_int32 * 4),
     ]
 
 

@@ -676,14 +676,15 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         if (dense::trace_sinv_a(S, L0, p, tr)) energy = tr;
     }
     // learned form: fall back to the paper preconditioner for fallback_hold
-    // iterations when the energy rises above the minimum of the last
-    // fallback_window iterates
+    // iterations when the energy rises above the minimum (rule 0) or the
+    // maximum (rule 1) of the last fallback_window iterates
     bool use_learned = learned_form && c->lp_hold == 0;
     int fell_back = 0;
     if (learned_form && std::isfinite(energy)) {
         if (use_learned && !c->ehist.empty()) {
-            const double mn = *std::min_element(c->ehist.begin(), c->ehist.end());
-            if (energy > mn + 1e-12 * std::fabs(energy)) {
+            const double ref = c->prm.fallback_rule == 1 ? *std::max_element(c->ehist.begin(), c->ehist.end())
+                                                         : *std::min_element(c->ehist.begin(), c->ehist.end());
+            if (energy > ref + 1e-12 * std::fabs(energy)) {
                 c->lp_hold = std::max(1, c->prm.fallback_hold);
                 use_learned = false;
                 fell_back = 1;
@@ -940,6 +941,7 @@ void ofks_default_params(ofks_params *p) {
     p->poisson_max_iter = 20000;
     p->fallback_window = 5;
     p->fallback_hold = 20;
+    p->fallback_rule = 0;
 }
 
 int ofks_create(ofks_ctx **out, void *hip_stream) {
@@ -1220,7 +1222,8 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
     if (!c || !prm) return OFKS_EINVAL;
     if (!(prm->beta >= 0.0) || !(prm->tol > 0.0) || prm->max_iter < 0 || prm->pcg_iters < 0 ||
         prm->precond < 0 || prm->precond > 2 || prm->step_rule < 0 || prm->step_rule > 4 ||
-        (prm->precision != OFKS_F64 && prm->precision != OFKS_F32))
+        (prm->precision != OFKS_F64 && prm->precision != OFKS_F32) || prm->fallback_rule < 0 ||
+        prm->fallback_rule > 1)
         return fail(c, OFKS_EINVAL, "set_params: invalid parameter");
     if (prm->precond == OFKS_PRECOND_PAPER && prm->pcg_iters < 1)
         return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs pcg_iters >= 1");

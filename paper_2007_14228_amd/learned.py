@@ -38,7 +38,7 @@ def init_weights(seed: int) -> np.ndarray:
 
 
 def collect(seeds, kind: str = "c2", target_dofs: int = 200_000, iters: int = 60, row_stride: int = 64,
-            cap: int = 40_000_000, log=print):
+            cap: int = 40_000_000, pcg_iters: int = 10, log=print):
     import torch
     sys.path.insert(0, os.path.dirname(HERE))
     import workloads as wl
@@ -50,7 +50,7 @@ def collect(seeds, kind: str = "c2", target_dofs: int = 200_000, iters: int = 60
         w = wl.make_workload(kind, seed=seed, target_dofs=target_dofs)
         s = Solver()
         s.load_workload(w)
-        s.set_params(beta=w.beta, tol=1e-30, max_iter=iters, precond="paper", pcg_iters=10,
+        s.set_params(beta=w.beta, tol=1e-30, max_iter=iters, precond="paper", pcg_iters=pcg_iters,
                      scf=1 if w.scf else 0, energy_every=10)
         X0 = torch.from_numpy(wl.random_block(seed, w.mesh.n_dofs, w.p)).cuda()
         s.set_x0(X0, orthonormalize=True)
