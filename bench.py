@@ -167,7 +167,7 @@ def main():
     dt = time.perf_counter() - t0
     if len(stats) != a.steps:
         raise RuntimeError("fewer steps than requested")
-    timers = {k: s.timer(k) for k in ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_xr", "pcg_dir",
+    timers = {k: s.timer(k) for k in ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_r", "pcg_dx",
                                       "bbdot", "density", "poisson", "assemble_h")}
     s.timing(False)
     log(f"{a.steps} steps in {dt:.3f}s; rel={stats[-1]['rel']:.3e}")

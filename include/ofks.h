@@ -238,7 +238,7 @@ int ofks_lp_apply(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, 
  * recording and clears the totals. */
 int ofks_timing(ofks_ctx *ctx, int32_t enable);
 /* Totals for a kernel class: name is one of "spmm_dual", "spmm_shift",
- * "gram", "update_a", "update_b", "pcg_xr", "pcg_dir", "density", "poisson",
+ * "gram", "update_a", "update_b", "pcg_r", "pcg_dx", "density", "poisson",
  * "assemble_h", "bbdot", "mlp", "mlp_train".  ms = summed duration, launches = count. */
 int ofks_timer_get(ofks_ctx *ctx, const char *name, double *ms, int64_t *launches);
 

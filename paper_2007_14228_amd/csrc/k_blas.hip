@@ -7,8 +7,8 @@
 //                epilogues (gradient of L_beta, residual norm for kkt, the
 //                start of the preconditioner's CG or the column norms of G
 //                for the learned form), or a plain Y = X M.
-//  k_pcg_xr      x += alpha d, r -= alpha q, <r, J r>   (inner CG step)
-//  k_pcg_dir     d = J r + beta d
+//  k_pcg_r       r -= alpha q, <r, J r>                  (inner CG step)
+//  k_pcg_dx      x += alpha d and d = J r + beta d
 //  k_pcg_scalars alpha / beta per column on the device
 //  k_bbdot       <S,Y>, <Y,Y>, <S,S>, ||P||^2, ||X||^2 for the BB step
 //  k_update_b    X~ = X - P / eta with X = X~ D^-1; keeps X as X^{k-1}
@@ -246,70 +246,54 @@ __global__ __launch_bounds__(256) void k_rowgemm(int64_t n, int p, int N, const 
 // Lane-per-column-slice kernels over n x p blocks (same mapping as SpMM).
 // ---------------------------------------------------------------------------
 
-// x = (first ? 0 : x) + alpha d ; r -= alpha q ; partial <r, J r>.  Persistent.
+// Inner CG of the paper preconditioner, split so that each block pass does
+// as much as the reductions allow:
+//   k_pcg_r   r -= alpha q, partial <r, J r>                (reads q, r; writes r)
+//   k_pcg_dx  x += alpha d, then d = J r + beta d          (reads d, r, x; writes d, x)
+//             or, in the last inner iteration, x += alpha d only
+// Per-column constants are held in registers; columns that are not active
+// (identity branch of eq. precondition-T) keep their stored x.
+
+// r -= alpha q on active columns; per-block partial <r, J r>.  Persistent.
 template <typename T, int V, int CH>
-__global__ __launch_bounds__(256) void k_pcg_xr(int64_t n, int p, int lpr_log2, int first,
-                                               const T *__restrict__ alpha,
-                                               const uint8_t *__restrict__ active,
-                                               const double *__restrict__ lhd,
-                                               const double *__restrict__ bd,
-                                               const T *__restrict__ lam, const T *__restrict__ D,
-                                               const T *__restrict__ Q, T *__restrict__ Xo,
-                                               T *__restrict__ R, double *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_pcg_r(int64_t n, int p, int lpr_log2, const T *__restrict__ alpha,
+                                              const uint8_t *__restrict__ active,
+                                              const double *__restrict__ lhd, const double *__restrict__ bd,
+                                              const T *__restrict__ lam, const T *__restrict__ Q,
+                                              T *__restrict__ R, double *__restrict__ part) {
     extern __shared__ double red[];
     const int lpr = 1 << lpr_log2;
     const int groups = blockDim.x >> lpr_log2;
     const int g = threadIdx.x >> lpr_log2;
     const int lane = threadIdx.x & (lpr - 1);
     double dot[CH][V];
+    T al[CH][V], lm[CH][V];
+    bool on[CH][V];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
-        for (int v = 0; v < V; ++v) dot[ch][v] = 0.0;
+        for (int v = 0; v < V; ++v) {
+            const int c = (lane + ch * lpr) * V + v;
+            on[ch][v] = c < p && active[c];
+            dot[ch][v] = 0.0;
+            al[ch][v] = on[ch][v] ? alpha[c] : T(0);   // inactive: r unchanged
+            lm[ch][v] = c < p ? lam[c] : T(0);
+        }
     for (int64_t row = (int64_t)blockIdx.x * groups + g; row < n; row += (int64_t)gridDim.x * groups) {
         const T ld = (T)lhd[row], bdv = (T)bd[row];
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
             const int c0 = (lane + ch * lpr) * V;
             if (c0 >= p) continue;
-            T d[V], q[V], x[V], r[V];
-            load_vec<T, V>(D + row * p + c0, d);
+            T q[V], r[V];
             load_vec<T, V>(Q + row * p + c0, q);
             load_vec<T, V>(R + row * p + c0, r);
-            if (first) {
-#pragma unroll
-                for (int v = 0; v < V; ++v) x[v] = T(0);
-            } else {
-                load_vec<T, V>(Xo + row * p + c0, x);
-            }
-            bool any = false;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                if (!active[c0 + v]) continue;
-                any = true;
-                const T a = alpha[c0 + v];
-                x[v] = fma(a, d[v], x[v]);
-                r[v] = fma(-a, q[v], r[v]);
-                const T z = r[v] / (ld - lam[c0 + v] * bdv);
-                dot[ch][v] += (double)r[v] * (double)z;
+                r[v] = fma(-al[ch][v], q[v], r[v]);
+                if (on[ch][v]) dot[ch][v] += (double)r[v] * (double)(r[v] / (ld - lm[ch][v] * bdv));
             }
-            if (any) {
-                // inactive columns of a vector keep their stored values
-                T xo[V], ro[V];
-                if (!first) {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) xo[v] = x[v];
-                } else {
-                    load_vec<T, V>(Xo + row * p + c0, xo);
-#pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        if (active[c0 + v]) xo[v] = x[v];
-                }
-#pragma unroll
-                for (int v = 0; v < V; ++v) ro[v] = r[v];
-                store_vec<T, V>(Xo + row * p + c0, xo);
-                store_vec<T, V>(R + row * p + c0, ro);
-            }
+            store_vec<T, V>(R + row * p + c0, r);
         }
     }
 #pragma unroll
@@ -328,28 +312,47 @@ __global__ __launch_bounds__(256) void k_pcg_xr(int64_t n, int p, int lpr_log2, 
     }
 }
 
-// d = J r + beta d on active columns.
-template <typename T, int V>
-__global__ __launch_bounds__(256) void k_pcg_dir(int64_t n, int p, int lpr_log2,
-                                                const T *__restrict__ beta,
-                                                const uint8_t *__restrict__ active,
-                                                const double *__restrict__ lhd,
-                                                const double *__restrict__ bd,
-                                                const T *__restrict__ lam, const T *__restrict__ R,
-                                                T *__restrict__ D) {
+// x = (first ? 0 : x) + alpha d on active columns; with DIR also
+// d = J r + beta d.  One lane group per row.
+template <typename T, int V, int DIR>
+__global__ __launch_bounds__(256) void k_pcg_dx(int64_t n, int p, int lpr_log2, int first,
+                                               const T *__restrict__ alpha, const T *__restrict__ beta,
+                                               const uint8_t *__restrict__ active,
+                                               const double *__restrict__ lhd, const double *__restrict__ bd,
+                                               const T *__restrict__ lam, const T *__restrict__ R,
+                                               T *__restrict__ D, T *__restrict__ X) {
     const int lpr = 1 << lpr_log2;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lpr_log2;
     const int lane = threadIdx.x & (lpr - 1);
     if (row >= n) return;
     const T ld = (T)lhd[row], bdv = (T)bd[row];
     for (int c0 = lane * V; c0 < p; c0 += lpr * V) {
-        T r[V], d[V];
-        load_vec<T, V>(R + row * p + c0, r);
-        load_vec<T, V>(D + row * p + c0, d);
+        bool on[V], all = true, any = false;
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-            if (active[c0 + v]) d[v] = fma(beta[c0 + v], d[v], r[v] / (ld - lam[c0 + v] * bdv));
-        store_vec<T, V>(D + row * p + c0, d);
+        for (int v = 0; v < V; ++v) {
+            on[v] = active[c0 + v] != 0;
+            all &= on[v];
+            any |= on[v];
+        }
+        if (!any) continue;
+        T d[V], x[V], r[V];
+        load_vec<T, V>(D + row * p + c0, d);
+        if (DIR) load_vec<T, V>(R + row * p + c0, r);
+        if (first && all) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) x[v] = T(0);
+        } else {
+            load_vec<T, V>(X + row * p + c0, x);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (!on[v]) continue;
+            const T a = alpha[c0 + v];
+            x[v] = first ? a * d[v] : fma(a, d[v], x[v]);
+            if (DIR) d[v] = fma(beta[c0 + v], d[v], r[v] / (ld - lam[c0 + v] * bdv));
+        }
+        store_vec<T, V>(X + row * p + c0, x);
+        if (DIR) store_vec<T, V>(D + row * p + c0, d);
     }
 }
 
@@ -668,11 +671,10 @@ hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int g
     } while (0)
 
 template <typename T>
-hipError_t launch_pcg_xr(hipStream_t s, int grid, int64_t n, int p, int first, const T *alpha,
-                         const uint8_t *active, const double *lhd, const double *bd, const T *lam,
-                         const T *D, const T *Q, T *X, T *R, double *part) {
+hipError_t launch_pcg_r(hipStream_t s, int grid, int64_t n, int p, const T *alpha, const uint8_t *active,
+                        const double *lhd, const double *bd, const T *lam, const T *Q, T *R, double *part) {
 #define SHM shm
-    OFKS_CH_DISPATCH(k_pcg_xr, first, alpha, active, lhd, bd, lam, D, Q, X, R, part);
+    OFKS_CH_DISPATCH(k_pcg_r, alpha, active, lhd, bd, lam, Q, R, part);
 #undef SHM
     return hipGetLastError();
 }
@@ -696,14 +698,25 @@ hipError_t launch_bbdot(hipStream_t s, int grid, int64_t n, int p, const T *Xt, 
 }
 
 template <typename T>
-hipError_t launch_pcg_dir(hipStream_t s, int64_t n, int p, const T *beta, const uint8_t *active,
-                          const double *lhd, const double *bd, const T *lam, const T *R, T *D) {
+hipError_t launch_pcg_dx(hipStream_t s, int64_t n, int p, int first, int dir, const T *alpha, const T *beta,
+                         const uint8_t *active, const double *lhd, const double *bd, const T *lam, const T *R,
+                         T *D, T *X) {
     const int v = vwidth<T>(p);
     const int l2 = lpr_l2(p, v);
     const unsigned grid = (unsigned)(((n << l2) + 255) / 256);
-    if (v == 1) hipLaunchKernelGGL((k_pcg_dir<T, 1>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D);
-    else if (v == 2) hipLaunchKernelGGL((k_pcg_dir<T, 2>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D);
-    else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_pcg_dir<T, 4>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D);
+#define OFKS_DX(VV)                                                                                        \
+    do {                                                                                                   \
+        if (dir)                                                                                           \
+            hipLaunchKernelGGL((k_pcg_dx<T, VV, 1>), dim3(grid), dim3(256), 0, s, n, p, l2, first, alpha, beta, \
+                               active, lhd, bd, lam, R, D, X);                                             \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_pcg_dx<T, VV, 0>), dim3(grid), dim3(256), 0, s, n, p, l2, first, alpha, beta, \
+                               active, lhd, bd, lam, R, D, X);                                             \
+    } while (0)
+    if (v == 1) OFKS_DX(1);
+    else if (v == 2) OFKS_DX(2);
+    else if constexpr (sizeof(T) == 4) OFKS_DX(4);
+#undef OFKS_DX
     return hipGetLastError();
 }
 
@@ -759,10 +772,10 @@ template hipError_t launch_pcg_init<float>(hipStream_t, int, int64_t, int, const
 #define OFKS_INST(T)                                                                                  \
     template hipError_t launch_gram<T>(hipStream_t, int64_t, int, const GramPlan &, const T *, const T *, const T *, double *, size_t); \
     template hipError_t launch_rowgemm<T>(hipStream_t, int, int64_t, int, int, int, const T *, const T *, const T *, T *, GradArgs, int *); \
-    template hipError_t launch_pcg_xr<T>(hipStream_t, int, int64_t, int, int, const T *, const uint8_t *, const double *, const double *, const T *, const T *, const T *, T *, T *, double *); \
+    template hipError_t launch_pcg_r<T>(hipStream_t, int, int64_t, int, const T *, const uint8_t *, const double *, const double *, const T *, const T *, T *, double *); \
     template hipError_t launch_coldot<T>(hipStream_t, int, int64_t, int, const T *, const T *, double *); \
     template hipError_t launch_bbdot<T>(hipStream_t, int, int64_t, int, const T *, const T *, const T *, const T *, const T *, double *); \
-    template hipError_t launch_pcg_dir<T>(hipStream_t, int64_t, int, const T *, const uint8_t *, const double *, const double *, const T *, const T *, T *); \
+    template hipError_t launch_pcg_dx<T>(hipStream_t, int64_t, int, int, int, const T *, const T *, const uint8_t *, const double *, const double *, const T *, const T *, T *, T *); \
     template hipError_t launch_update_b<T>(hipStream_t, int64_t, int, const T *, T, const T *, T *, T *); \
     template hipError_t launch_pcg_scalars<T>(hipStream_t, int, int, const double *, double *, T *);
 OFKS_INST(double)

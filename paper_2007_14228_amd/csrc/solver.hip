@@ -69,16 +69,16 @@ hipError_t launch_rowgemm(hipStream_t, int, int64_t, int, int, int, const T *, c
                           GradArgs, int *);
 int rowgemm_tile_cols(int N);
 template <typename T>
-hipError_t launch_pcg_xr(hipStream_t, int, int64_t, int, int, const T *, const uint8_t *, const double *,
-                         const double *, const T *, const T *, const T *, T *, T *, double *);
+hipError_t launch_pcg_r(hipStream_t, int, int64_t, int, const T *, const uint8_t *, const double *, const double *,
+                        const T *, const T *, T *, double *);
 template <typename T>
 hipError_t launch_coldot(hipStream_t, int, int64_t, int, const T *, const T *, double *);
 template <typename T>
 hipError_t launch_bbdot(hipStream_t, int, int64_t, int, const T *, const T *, const T *, const T *, const T *,
                         double *);
 template <typename T>
-hipError_t launch_pcg_dir(hipStream_t, int64_t, int, const T *, const uint8_t *, const double *, const double *,
-                          const T *, const T *, T *);
+hipError_t launch_pcg_dx(hipStream_t, int64_t, int, int, int, const T *, const T *, const uint8_t *, const double *,
+                         const double *, const T *, const T *, T *, T *);
 template <typename T>
 hipError_t launch_update_b(hipStream_t, int64_t, int, const T *, T, const T *, T *, T *);
 template <typename T>
@@ -580,6 +580,36 @@ double bb_eta(int rule, int k, double sy, double yy, double ss, double eta_prev,
 // ---------------------------------------------------------------------------
 // one PCAL iteration
 // ---------------------------------------------------------------------------
+// P = T^-1 G columnwise by m Jacobi-PCG iterations from zero (eq. precondition-T).
+// On entry R = G and D = J G on active columns, rz = <G, J G>; X holds the
+// identity-branch columns already.  Q is scratch for the operator output.
+template <typename T>
+int pcg_run(ofks_ctx *c, int m, int64_t n, int p, const uint8_t *act, const T *lam, const void *lb, T *D, T *Q, T *X,
+            T *R, T *alpha, T *beta, double *rz) {
+    CHK(ensure_part(c, (size_t)c->grid * p));
+    for (int it = 0; it < m; ++it) {
+        int used = 0;
+        {
+            Scope sc(c, "spmm_shift");
+            HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, n, p, c->rp, c->col, lb, lam, act, D, Q, c->part, &used));
+        }
+        HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
+        HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, rz, alpha));
+        const bool more = it + 1 < m;   // the last iteration needs no new residual or direction
+        if (more) {
+            {
+                Scope sc(c, "pcg_r");
+                HIPCHK(launch_pcg_r<T>(c->stream, c->grid, n, p, alpha, act, c->lhd, c->bd, lam, Q, R, c->part));
+            }
+            HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+            HIPCHK(launch_pcg_scalars<T>(c->stream, p, 1, c->red, rz, beta));
+        }
+        Scope sc(c, "pcg_dx");
+        HIPCHK(launch_pcg_dx<T>(c->stream, n, p, it == 0, more, alpha, beta, act, c->lhd, c->bd, lam, R, D, X));
+    }
+    return OFKS_OK;
+}
+
 template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) {
     Blocks<T> &B = blk<T>(c);
     const int p = c->p;
@@ -775,28 +805,8 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     // preconditioner: columnwise Jacobi-PCG from zero, fixed iteration count
     if (use_paper && any_active) {
         CHK(upload_bytes(c, c->rz, r2.data() + 1, p * sizeof(double)));
-        CHK(ensure_part(c, (size_t)c->grid * p));
-        for (int it = 0; it < c->prm.pcg_iters; ++it) {
-            int used = 0;
-            {
-                Scope sc(c, "spmm_shift");
-                HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, n, p, c->rp, c->col, lbT<T>(c), B.lam, c->active,
-                                            B.D, B.HX, c->part, &used));
-            }
-            HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
-            HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, c->rz, B.alpha));
-            {
-                Scope sc(c, "pcg_xr");
-                HIPCHK(launch_pcg_xr<T>(c->stream, c->grid, n, p, it == 0, B.alpha, c->active, c->lhd, c->bd,
-                                        B.lam, B.D, B.HX, B.P, B.R, c->part));
-            }
-            HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
-            if (it + 1 < c->prm.pcg_iters) {
-                HIPCHK(launch_pcg_scalars<T>(c->stream, p, 1, c->red, c->rz, B.beta));
-                Scope sc(c, "pcg_dir");
-                HIPCHK(launch_pcg_dir<T>(c->stream, n, p, B.beta, c->active, c->lhd, c->bd, B.lam, B.R, B.D));
-            }
-        }
+        CHK(pcg_run<T>(c, c->prm.pcg_iters, n, p, c->active, B.lam, lbT<T>(c), B.D, B.HX, B.P, B.R, B.alpha, B.beta,
+                       c->rz));
     }
     if (collect) {
         // t = T^-1 g (this step's P), weights 1 / mean_i t_il^2, every lp_stride-th row
@@ -1484,20 +1494,7 @@ int ofks_precondition(ofks_ctx *c, int32_t p, const double *lam, const double *G
     CHK(ensure_part(c, (size_t)c->grid * p));
     HIPCHK(launch_pcg_init<double>(c->stream, c->grid, n, p, act, c->lhd, c->bd, lamd, G, R, D, P, c->part));
     HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, rzd));
-    for (int it = 0; it < m; ++it) {
-        int used = 0;
-        HIPCHK(launch_spmm_shift<double>(c->stream, c->grid, n, p, c->rp, c->col, c->lb, lamd, act, D, Q, c->part,
-                                         &used));
-        HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
-        HIPCHK(launch_pcg_scalars<double>(c->stream, p, 0, c->red, rzd, alpha));
-        HIPCHK(launch_pcg_xr<double>(c->stream, c->grid, n, p, it == 0, alpha, act, c->lhd, c->bd, lamd, D, Q, P, R,
-                                     c->part));
-        HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
-        if (it + 1 < m) {
-            HIPCHK(launch_pcg_scalars<double>(c->stream, p, 1, c->red, rzd, betad));
-            HIPCHK(launch_pcg_dir<double>(c->stream, n, p, betad, act, c->lhd, c->bd, lamd, R, D));
-        }
-    }
+    CHK(pcg_run<double>(c, m, n, p, act, lamd, c->lb, D, Q, P, R, alpha, betad, rzd));
     CHK(sync(c));
     dfree(c, R);
     dfree(c, D);
