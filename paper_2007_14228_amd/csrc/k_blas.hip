@@ -243,6 +243,166 @@ __global__ __launch_bounds__(256) void k_rowgemm(int64_t n, int p, int N, const 
 }
 
 // ---------------------------------------------------------------------------
+// The same row GEMM on the matrix cores (16x16x4 MFMA, FP64 or FP32).
+// Block: 4 waves, 64 rows x TC = 16 NTW columns; wave w owns rows 16w..16w+15
+// of the tile and all NTW 16x16 output tiles.  A (scaled by sa) and M are
+// staged through LDS in K-chunks of 16 (zero-filled past p, N and n), so any
+// shape works.  Operand layout of the 16x16x4 instructions (lane l, measured
+// on gfx950): A[l % 16][l / 16], B[l / 16][l % 16]; result slot i < 4 holds
+// D[4 (l / 16) + i][l % 16] for f32 and D[l / 16 + 4 i][l % 16] for f64.
+// Epilogues and per-block partials as in k_rowgemm.
+// ---------------------------------------------------------------------------
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct mfma4;
+template <> struct mfma4<double> { using type = mfma_d4; };
+template <> struct mfma4<float> { using type = mfma_f4; };
+__device__ __forceinline__ mfma_d4 mfma16x16x4(double a, double b, mfma_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mfma_f4 mfma16x16x4(float a, float b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// row (within the 16 x 16 tile) of result slot i of lane group lk = l / 16
+template <typename T> __device__ __forceinline__ int mfma_row(int lk, int i) {
+    return sizeof(T) == 8 ? lk + 4 * i : 4 * lk + i;
+}
+
+template <typename T, int NTW, int EPI>
+__global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A,
+                                                     const T *__restrict__ sa, const T *__restrict__ M,
+                                                     T *__restrict__ Y, GradArgs ga) {
+    constexpr int TR = 64, TC = 16 * NTW, KC = 16;
+    using acc_t = typename mfma4<T>::type;
+    __shared__ T As[TR][KC + 1];
+    __shared__ T Ms[KC][TC];
+    __shared__ double red[256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int c0 = blockIdx.y * TC;
+    const int64_t ntiles = (n + TR - 1) / TR;
+    double r2 = 0.0;
+    double rz[NTW];
+    // this lane's output columns are fixed for the whole launch
+    T scl[NTW], lmc[NTW];
+    bool act[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        rz[t] = 0.0;
+        const int c = c0 + 16 * t + li;
+        const int cc = c < p ? c : c - p;
+        scl[t] = (EPI != EPI_PLAIN && c < N) ? sa[cc] : T(0);
+        lmc[t] = (EPI == EPI_GRAD_PCG && c < p) ? ((const T *)ga.lam)[c] : T(0);
+        act[t] = (EPI == EPI_GRAD_PCG && c < p) ? ga.active[c] != 0 : false;
+    }
+    const T *__restrict__ HX = (const T *)ga.HX;
+    T *__restrict__ Pout = (T *)ga.P;
+    T *__restrict__ Rout = (T *)ga.R;
+    T *__restrict__ Dout = (T *)ga.D;
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * TR;
+        acc_t acc[NTW];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) acc[t] = acc_t{T(0), T(0), T(0), T(0)};
+        for (int k0 = 0; k0 < p; k0 += KC) {
+            for (int idx = threadIdx.x; idx < TR * KC; idx += 256) {
+                const int rr = idx / KC, kk = idx % KC;
+                const int64_t r = r0 + rr;
+                const int k = k0 + kk;
+                As[rr][kk] = (r < n && k < p) ? A[r * p + k] * sa[k] : T(0);
+            }
+            for (int idx = threadIdx.x; idx < KC * TC; idx += 256) {
+                const int kk = idx / TC, cc = idx % TC;
+                const int k = k0 + kk, c = c0 + cc;
+                Ms[kk][cc] = (k < p && c < N) ? M[(int64_t)k * N + c] : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s4 = 0; s4 < KC / 4; ++s4) {
+                const T a = As[16 * w + li][4 * s4 + lk];
+#pragma unroll
+                for (int t = 0; t < NTW; ++t) acc[t] = mfma16x16x4(a, Ms[4 * s4 + lk][16 * t + li], acc[t]);
+            }
+            __syncthreads();
+        }
+        // epilogue: lane holds rows r0 + 16w + mfma_row(lk, i) of column c0 + 16 t + li
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = r0 + 16 * w + mfma_row<T>(lk, i);
+            if (r >= n) continue;
+            T ld = T(0), bdv = T(0);
+            if (EPI == EPI_GRAD_PCG) {
+                ld = T(ga.lhd[r]);
+                bdv = T(ga.bd[r]);
+            }
+            T hx[NTW];
+            if (EPI != EPI_PLAIN) {
+#pragma unroll
+                for (int t = 0; t < NTW; ++t) {
+                    const int c = c0 + 16 * t + li;
+                    hx[t] = c < N ? HX[r * p + (c < p ? c : c - p)] : T(0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                const int c = c0 + 16 * t + li;
+                if (c >= N) continue;
+                const T val = acc[t][i];
+                if (EPI == EPI_PLAIN) {
+                    Y[r * N + c] = val;
+                    continue;
+                }
+                const T v = fma(hx[t], scl[t], val);
+                if (c >= p) {
+                    r2 += (double)v * (double)v;
+                } else if (EPI == EPI_GRAD) {
+                    Pout[r * p + c] = v;
+                } else if (EPI == EPI_GRAD_NORM) {
+                    Pout[r * p + c] = v;
+                    rz[t] += (double)v * (double)v;
+                } else {  // EPI_GRAD_PCG
+                    if (act[t]) {
+                        const T z = v * (T(1) / (ld - lmc[t] * bdv));
+                        Rout[r * p + c] = v;
+                        Dout[r * p + c] = z;
+                        rz[t] += (double)v * (double)z;
+                    } else {
+                        Pout[r * p + c] = v;
+                    }
+                }
+            }
+        }
+    }
+    if (EPI == EPI_PLAIN) return;
+    double *part = ga.part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (1 + p);
+    red[threadIdx.x] = r2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[0] = red[0];
+    __syncthreads();
+    if (EPI == EPI_GRAD_PCG || EPI == EPI_GRAD_NORM) {
+        for (int c = threadIdx.x; c < p; c += 256)
+            if (c < c0 || c >= c0 + TC) part[1 + c] = 0.0;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            red[threadIdx.x] = rz[t];   // [w][lk][li]
+            __syncthreads();
+            if (threadIdx.x < 16) {
+                double sum = 0.0;
+                for (int k = 0; k < 16; ++k) sum += red[k * 16 + threadIdx.x];
+                const int c = c0 + 16 * t + threadIdx.x;
+                if (c < p) part[1 + c] = sum;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Lane-per-column-slice kernels over n x p blocks (same mapping as SpMM).
 // ---------------------------------------------------------------------------
 
@@ -617,7 +777,13 @@ hipError_t launch_colsum(hipStream_t s, int64_t nb, int64_t m, const double *par
 }
 
 // Column tile width of k_rowgemm for N output columns (16 * NT).
-int rowgemm_tile_cols(int N) { return N <= 16 ? 16 : (N <= 32 ? 32 : 64); }
+#ifndef OFKS_RG_TC_MAX
+#define OFKS_RG_TC_MAX 128
+#endif
+int rowgemm_tile_cols(int N) {
+    const int tc = N <= 16 ? 16 : (N <= 32 ? 32 : (N <= 64 ? 64 : (N <= 128 ? 128 : 256)));
+    return tc < OFKS_RG_TC_MAX ? tc : OFKS_RG_TC_MAX;
+}
 
 // number of blocks along rows for k_rowgemm epilogues (fixed => deterministic)
 template <typename T>
@@ -644,8 +810,19 @@ hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int g
     }
     OFKS_RG(4, 1)
     OFKS_RG(4, 2)
-    OFKS_RG(4, 4)
 #undef OFKS_RG
+#define OFKS_RGM(NTW_)                                                                        \
+    if (nt == NTW_) {                                                                         \
+        if (epi == EPI_PLAIN) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_PLAIN>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else if (epi == EPI_GRAD_NORM) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD_NORM>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD_PCG>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+        return hipGetLastError();                                                             \
+    }
+    OFKS_RGM(4)
+    OFKS_RGM(8)
+    OFKS_RGM(16)
+#undef OFKS_RGM
     return hipErrorInvalidValue;
 }
 

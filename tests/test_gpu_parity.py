@@ -140,6 +140,41 @@ def test_first_iterations_follow_the_oracle(precond, c1):
         assert abs(st[k - 1]["eta"] - hist[k].eta) <= 1e-9 * hist[k].eta
 
 
+@pytest.mark.parametrize("p", [40, 128, 130])
+def test_first_iterations_follow_the_oracle_wide_blocks(p, c1):
+    """Step parity at block widths where the row GEMM runs on the matrix cores
+    (p = 130: a ragged last column tile), paper preconditioner, FP64."""
+    w, d = c1
+    print(f"[gpu] step parity c1 p={p}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(5, d.n, p))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=3, precond="paper"))
+    s = _solver_for(w)
+    st = _run_gpu(s, X0, 3, beta=w.beta, tol=1e-30, precond="paper", pcg_iters=10, energy_every=1)
+    assert len(st) == len(hist) == 4
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-10 * b.kkt
+        assert abs(a["energy"] - b.energy) <= 1e-11 * abs(b.energy)
+
+
+@pytest.mark.parametrize("p", [40, 130])
+def test_fp32_iterations_stay_close_to_the_oracle(p, c1):
+    """The FP32 block path (FP32 matrix-core products) tracks the FP64 oracle
+    over the first iterations to FP32 accuracy."""
+    w, d = c1
+    print(f"[gpu] fp32 step c1 p={p}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(6, d.n, p))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=2, precond="paper"))
+    s = _solver_for(w)
+    st = _run_gpu(s, X0, 2, beta=w.beta, tol=1e-30, precond="paper", pcg_iters=10, energy_every=1,
+                  precision="f32")
+    assert st[0]["precision"] == 1
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-4 * b.kkt
+        assert abs(a["energy"] - b.energy) <= 1e-5 * abs(b.energy)
+
+
 @pytest.mark.parametrize("precond", ["none", "paper"])
 def test_converged_eigenvalues_match_dense_lapack(precond, c1):
     w, d = c1
