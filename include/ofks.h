@@ -74,7 +74,7 @@ typedef struct {
     double refine_tol;      /* F32 only: switch to FP64 when rel < refine_tol (0: never) */
     double poisson_rtol;    /* Hartree CG relative residual */
     int32_t poisson_max_iter;
-    int32_t fallback_window;/* learned form: W iterations of energy history */
+    int32_t fallback_window;/* learned form: W iterations of energy history (<= 0: no fallback) */
     int32_t fallback_hold;  /* learned form: iterations on the paper preconditioner after a fallback */
     int32_t fallback_rule;  /* learned form: a fallback when E^k exceeds 0: the minimum, 1: the maximum
                                of the previous fallback_window energies */
@@ -206,12 +206,18 @@ int ofks_lp_set_weights(ofks_ctx *ctx, const float *host_w, const float *host_no
 
 /* Training-sample collection: while dev_buf != NULL, every iteration that
  * applies the paper preconditioner appends, for every row_stride-th row and
- * all columns, one sample of 8 floats [4 raw features, a = J g, t = (T^-1 g),
- * w = 1/mean_i t_il^2, 0] to dev_buf (device, capacity cap samples).
+ * all columns, one sample of 8 floats [4 raw features, a, t, w, 0] of the
+ * weighted least-squares fit of exp(f) a to t (dev_buf: device, capacity cap
+ * samples).  objective 0 imitates T^-1 g in the Euclidean norm: a = J g,
+ * t = T^-1 g (the paper preconditioner's output), w = 1/mean_i t_il^2.
+ * objective 1 imitates it in the energy norm of T with the scale taken as
+ * locally constant, i.e. minimizes the quadratic model d^T T d / 2 - g^T d
+ * over d = s J g node by node: a = 1, t = g/u, w = max(J g u, 0) n/<g, T^-1 g>
+ * with u = T J g (u = g on identity-branch columns).
  * A new dev_buf restarts the count at zero; dev_buf = NULL stops collection
  * and leaves the count of the last buffer readable through
  * ofks_lp_collected.  The buffer is caller-owned. */
-int ofks_lp_collect(ofks_ctx *ctx, int64_t row_stride, float *dev_buf, int64_t cap);
+int ofks_lp_collect(ofks_ctx *ctx, int64_t row_stride, int32_t objective, float *dev_buf, int64_t cap);
 int ofks_lp_collected(ofks_ctx *ctx, int64_t *count);
 
 /* Trains on m device samples: standardization from the samples (norm_out,

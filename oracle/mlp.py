@@ -11,6 +11,13 @@ Definition (FP64 here; the library evaluates it in FP32):
 Parameter vector: [W1 row-major (128), b1 (32), W2 (32), b2 (1)] = 193 values.
 Training objective over samples s = (feat, a, t, w):
   loss = sum_s w_s (exp(f_s) a_s - t_s)^2
+Samples of one iterate (rows i, columns l; g = G_il, a = J_il g, t = (T_l^-1 G_l)_i):
+  Euclidean imitation:    (a, t, n / sum_i t_il^2)
+  energy-norm imitation:  (1, g / u, max(a u, 0) n / <G_l, T_l^-1 G_l>),  u = (T_l J_l G_l)_i
+The second is the quadratic model d^T T d / 2 - g^T d of the paper's operator
+T (eq. precondition-T) over d = s J g with the scale s taken as locally
+constant: sum_i a_i u_i (s_i - g_i / u_i)^2 equals ||s J g - T^-1 g||_T^2 up
+to a term without s when s is constant.
 """
 from __future__ import annotations
 
@@ -86,3 +93,23 @@ def init_weights(seed: int) -> np.ndarray:
     W[:4 * H] = rng.standard_normal(4 * H) * 0.5
     W[4 * H:5 * H] = rng.standard_normal(H) * 0.1
     return W
+
+
+def samples(lhd, bd, hd, lam, G, t, u, objective: str, clamp: bool = True):
+    """Samples [n, p, 7] = (4 raw features, a, t, w) of every (row, column).
+    t: the paper preconditioner's output for G; u: T (J G) columnwise (G on
+    identity-branch columns).  clamp=False keeps negative energy weights (pins only)."""
+    n, p = G.shape
+    a = jacobi(lhd, bd, lam) * G
+    F = features(lhd, bd, hd, G)
+    if objective == "euclid":
+        A, Tt = a, t
+        W = np.broadcast_to(n / np.sum(t * t, axis=0), (n, p))
+    else:
+        A = np.ones((n, p))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Tt = np.where(u != 0, G / u, 0.0)
+        au = a * u
+        W = (np.maximum(au, 0.0) if clamp else au) * (n / np.sum(G * t, axis=0))[None, :]
+        W = np.where(u != 0, W, 0.0)
+    return np.concatenate([F, A[..., None], Tt[..., None], W[..., None]], axis=2)

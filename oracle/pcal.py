@@ -211,13 +211,15 @@ def pcal(prob, X0: np.ndarray, params: Params,
         kind = params.precond
         if params.precond == "learned":
             # fall back to the paper preconditioner for fallback_hold steps when
-            # E^k exceeds the minimum (or maximum) of the previous fallback_window energies
+            # E^k exceeds the minimum (or maximum) of the previous fallback_window
+            # energies; fallback_window <= 0: never
             use_learned = hold == 0
-            ref = (max if params.fallback_rule == "max" else min)(ehist) if ehist else None
-            if use_learned and ehist and E > ref + 1e-12 * abs(E):
-                hold = max(1, params.fallback_hold)
-                use_learned = False
-            ehist = (ehist + [E])[-max(1, params.fallback_window):]
+            if params.fallback_window > 0:
+                ref = (max if params.fallback_rule == "max" else min)(ehist) if ehist else None
+                if use_learned and ehist and E > ref + 1e-12 * abs(E):
+                    hold = max(1, params.fallback_hold)
+                    use_learned = False
+                ehist = (ehist + [E])[-params.fallback_window:]
             kind = "learned" if use_learned else "paper"
             if hold > 0 and not use_learned:
                 hold -= 1

@@ -84,7 +84,7 @@ SIGNATURES = [
     ("ofks_precondition", I32, [P, I32, P, P, P]),
     ("ofks_build_hamiltonian", I32, [P, I32, P, P, P, P, P, P]),
     ("ofks_lp_set_weights", I32, [P, P, P]),
-    ("ofks_lp_collect", I32, [P, I64, P, I64]),
+    ("ofks_lp_collect", I32, [P, I64, I32, P, I64]),
     ("ofks_lp_collected", I32, [P, ctypes.POINTER(I64)]),
     ("ofks_lp_train", I32, [P, P, I64, I32, ctypes.c_float, P, P, P]),
     ("ofks_lp_loss_grad", I32, [P, P, I64, P, P, ctypes.POINTER(_c_double), P]),

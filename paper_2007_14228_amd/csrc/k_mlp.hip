@@ -72,13 +72,20 @@ __global__ __launch_bounds__(256) void k_lp_apply(int64_t n, int p, int lpr_log2
     }
 }
 
-// Training samples from rows i = offset + j * stride (all columns): raw
-// features, a = J g, t = P (the paper preconditioner's output), and weight
-// w = 1 / (mean_i t_il^2) given per column in tw.  Slot (j * p + c) after base.
+// Training samples from rows i = offset + j * stride (all columns), slot
+// (j * p + c) after base: raw features, then (a, t, w) of the weighted
+// least-squares fit of exp(f) a to t:
+//  objective 0 (Euclidean imitation): a = J g, t = P (the paper
+//    preconditioner's output T^-1 g), w = tw_c = 1 / mean_i t_ic^2;
+//  objective 1 (imitation in the energy norm of T, with the scale taken as
+//    locally constant): a = 1, t = g / u, w = tw_c max(J g u, 0), where
+//    u = T (J g) (U, active columns; u = g on identity-branch columns) and
+//    tw_c = n / <g_c, t_c>.
 template <typename T>
-__global__ void k_lp_sample(int64_t n, int p, int64_t offset, int64_t stride, int64_t rows,
-                            const T *__restrict__ G, const T *__restrict__ P, const double *__restrict__ lhd,
-                            const double *__restrict__ bd, const double *__restrict__ hd, const T *__restrict__ lam,
+__global__ void k_lp_sample(int64_t n, int p, int64_t offset, int64_t stride, int64_t rows, int objective,
+                            const T *__restrict__ G, const T *__restrict__ P, const T *__restrict__ U,
+                            const double *__restrict__ lhd, const double *__restrict__ bd,
+                            const double *__restrict__ hd, const T *__restrict__ lam,
                             const uint8_t *__restrict__ negl, const double *__restrict__ g2,
                             const double *__restrict__ tw, float *__restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,9 +103,18 @@ __global__ void k_lp_sample(int64_t n, int p, int64_t offset, int64_t stride, in
     o[1] = (float)log(b);
     o[2] = (float)((hd[i] - l2) / b);
     o[3] = rms > 0.0f ? (float)g / rms : 0.0f;
-    o[4] = (float)(J * g);
-    o[5] = (float)P[i * p + c];
-    o[6] = (float)tw[c];
+    if (objective == 0) {
+        o[4] = (float)(J * g);
+        o[5] = (float)P[i * p + c];
+        o[6] = (float)tw[c];
+    } else {
+        const double a = (double)(J * g);
+        const double u = negl[c] ? (double)U[i * p + c] : (double)g;
+        const double au = a * u;
+        o[4] = 1.0f;
+        o[5] = u != 0.0 ? (float)((double)g / u) : 0.0f;
+        o[6] = (u != 0.0 && au > 0.0) ? (float)(tw[c] * au) : 0.0f;
+    }
     o[7] = 0.0f;
 }
 
@@ -215,12 +231,14 @@ hipError_t launch_lp_apply(hipStream_t s, int64_t n, int p, T *P, const double *
 
 template <typename T>
 hipError_t launch_lp_sample(hipStream_t s, int64_t n, int p, int64_t offset, int64_t stride, int64_t rows,
-                            const T *G, const T *P, const double *lhd, const double *bd, const double *hd,
-                            const T *lam, const uint8_t *negl, const double *g2, const double *tw, float *out) {
+                            int objective, const T *G, const T *P, const T *U, const double *lhd, const double *bd,
+                            const double *hd, const T *lam, const uint8_t *negl, const double *g2, const double *tw,
+                            float *out) {
     const int64_t tot = rows * p;
     if (tot <= 0) return hipSuccess;
+    if (objective != 0 && !U) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_lp_sample<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, p, offset, stride,
-                       rows, G, P, lhd, bd, hd, lam, negl, g2, tw, out);
+                       rows, objective, G, P, U, lhd, bd, hd, lam, negl, g2, tw, out);
     return hipGetLastError();
 }
 
@@ -247,12 +265,13 @@ template hipError_t launch_lp_apply<double>(hipStream_t, int64_t, int, double *,
 template hipError_t launch_lp_apply<float>(hipStream_t, int64_t, int, float *, const double *, const double *,
                                            const double *, const float *, const uint8_t *, const double *,
                                            const float *, const float *);
-template hipError_t launch_lp_sample<double>(hipStream_t, int64_t, int, int64_t, int64_t, int64_t, const double *,
+template hipError_t launch_lp_sample<double>(hipStream_t, int64_t, int, int64_t, int64_t, int64_t, int,
                                              const double *, const double *, const double *, const double *,
-                                             const double *, const uint8_t *, const double *, const double *,
-                                             float *);
-template hipError_t launch_lp_sample<float>(hipStream_t, int64_t, int, int64_t, int64_t, int64_t, const float *,
-                                            const float *, const double *, const double *, const double *,
-                                            const float *, const uint8_t *, const double *, const double *, float *);
+                                             const double *, const double *, const double *, const uint8_t *,
+                                             const double *, const double *, float *);
+template hipError_t launch_lp_sample<float>(hipStream_t, int64_t, int, int64_t, int64_t, int64_t, int, const float *,
+                                            const float *, const float *, const double *, const double *,
+                                            const double *, const float *, const uint8_t *, const double *,
+                                            const double *, float *);
 
 }  // namespace ofks

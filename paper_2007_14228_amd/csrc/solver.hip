@@ -115,8 +115,8 @@ template <typename T>
 hipError_t launch_lp_apply(hipStream_t, int64_t, int, T *, const double *, const double *, const double *, const T *,
                            const uint8_t *, const double *, const float *, const float *);
 template <typename T>
-hipError_t launch_lp_sample(hipStream_t, int64_t, int, int64_t, int64_t, int64_t, const T *, const T *,
-                            const double *, const double *, const double *, const T *, const uint8_t *,
+hipError_t launch_lp_sample(hipStream_t, int64_t, int, int64_t, int64_t, int64_t, int, const T *, const T *,
+                            const T *, const double *, const double *, const double *, const T *, const uint8_t *,
                             const double *, const double *, float *);
 hipError_t launch_lp_grad(hipStream_t, int, int64_t, const float *, const float *, const float *, double *);
 hipError_t launch_lp_adam(hipStream_t, const double *, double, float *, float *, float *, float, float, float, float,
@@ -226,6 +226,9 @@ struct ofks_ctx {
     double *g2 = nullptr, *tw = nullptr;
     float *lp_buf = nullptr;     // training-sample collection
     int64_t lp_cap = 0, lp_count = 0, lp_stride = 0;
+    int lp_objective = 0;        // 0: Euclidean imitation of T^-1 g, 1: energy-norm imitation
+    void *lp_u = nullptr;        // T (J G) for the energy-norm samples
+    size_t lp_u_bytes = 0;
 
     // timing
     bool timing = false;
@@ -707,10 +710,11 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     }
     // learned form: fall back to the paper preconditioner for fallback_hold
     // iterations when the energy rises above the minimum (rule 0) or the
-    // maximum (rule 1) of the last fallback_window iterates
+    // maximum (rule 1) of the last fallback_window iterates (no fallback when
+    // fallback_window <= 0)
     bool use_learned = learned_form && c->lp_hold == 0;
     int fell_back = 0;
-    if (learned_form && std::isfinite(energy)) {
+    if (learned_form && c->prm.fallback_window > 0 && std::isfinite(energy)) {
         if (use_learned && !c->ehist.empty()) {
             const double ref = c->prm.fallback_rule == 1 ? *std::max_element(c->ehist.begin(), c->ehist.end())
                                                          : *std::min_element(c->ehist.begin(), c->ehist.end());
@@ -721,7 +725,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
             }
         }
         c->ehist.push_back(energy);
-        const size_t W = (size_t)std::max(1, c->prm.fallback_window);
+        const size_t W = (size_t)c->prm.fallback_window;
         while (c->ehist.size() > W) c->ehist.erase(c->ehist.begin());
     }
     const bool use_paper = c->prm.precond == OFKS_PRECOND_PAPER || (learned_form && !use_learned);
@@ -800,6 +804,24 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         HIPCHK(launch_colsum(c->stream, (int64_t)gx * gy, 1 + p, c->part, c->red));
         HIPCHK(hipMemcpyAsync(c->g2, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(B.BX, B.P, (size_t)n * p * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        if (c->lp_objective == 1) {
+            // u = T (J G): D holds J G on the active columns here
+            const size_t bytes = (size_t)n * p * sizeof(T);
+            if (c->lp_u_bytes < bytes) {
+                char *u = (char *)c->lp_u;
+                if (u) CHK(sync(c));   // the previous buffer may still be read by queued work
+                dfree(c, u);
+                c->lp_u = nullptr;
+                c->lp_u_bytes = 0;
+                CHK(dalloc(c, &u, bytes));
+                c->lp_u = u;
+                c->lp_u_bytes = bytes;
+            }
+            CHK(ensure_part(c, (size_t)c->grid * p));
+            int used = 0;
+            HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, n, p, c->rp, c->col, lbT<T>(c), B.lam, c->active, B.D,
+                                        (T *)c->lp_u, c->part, &used));
+        }
     }
 
     // preconditioner: columnwise Jacobi-PCG from zero, fixed iteration count
@@ -809,9 +831,10 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
                        c->rz));
     }
     if (collect) {
-        // t = T^-1 g (this step's P), weights 1 / mean_i t_il^2, every lp_stride-th row
+        // t = T^-1 g (this step's P), every lp_stride-th row; per-column weights
+        // n / <t, t> (objective 0) or n / <g, t> (objective 1)
         std::vector<double> pp;
-        CHK(coldot<T>(c, B.P, B.P, pp));
+        CHK(coldot<T>(c, c->lp_objective == 1 ? B.BX : B.P, B.P, pp));
         std::vector<double> w(p);
         for (int i = 0; i < p; ++i) w[i] = pp[i] > 0 ? (double)n / pp[i] : 0.0;
         CHK(upload<double>(c, c->tw, w));
@@ -820,8 +843,9 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         int64_t rows = (n - offset + stride - 1) / stride;
         rows = std::min<int64_t>(rows, (c->lp_cap - c->lp_count) / p);
         if (rows > 0) {
-            HIPCHK(launch_lp_sample<T>(c->stream, n, p, offset, stride, rows, B.BX, B.P, c->lhd, c->bd, c->hd, B.lam,
-                                       c->active, c->g2, c->tw, c->lp_buf + c->lp_count * LP_SAMPLE));
+            HIPCHK(launch_lp_sample<T>(c->stream, n, p, offset, stride, rows, c->lp_objective, B.BX, B.P,
+                                       (const T *)c->lp_u, c->lhd, c->bd, c->hd, B.lam, c->active, c->g2, c->tw,
+                                       c->lp_buf + c->lp_count * LP_SAMPLE));
             c->lp_count += rows * p;
         }
     }
@@ -1552,9 +1576,11 @@ int ofks_lp_set_weights(ofks_ctx *c, const float *w, const float *norm) {
     return OFKS_OK;
 }
 
-int ofks_lp_collect(ofks_ctx *c, int64_t row_stride, float *dev_buf, int64_t cap) {
+int ofks_lp_collect(ofks_ctx *c, int64_t row_stride, int32_t objective, float *dev_buf, int64_t cap) {
     if (!c) return OFKS_EINVAL;
     if (dev_buf && (cap <= 0 || row_stride <= 0)) return fail(c, OFKS_EINVAL, "lp_collect: bad capacity or stride");
+    if (objective != 0 && objective != 1) return fail(c, OFKS_EINVAL, "lp_collect: objective must be 0 or 1");
+    c->lp_objective = objective;
     c->lp_buf = dev_buf;
     c->lp_cap = dev_buf ? cap : 0;
     c->lp_stride = row_stride;

@@ -2,8 +2,9 @@
 
 1. Collect samples: run the plain method (FP64, the paper preconditioner) on
    seeded training workloads; while it iterates, the library records
-   (features, J g, T^-1 g, weight) for every `row_stride`-th row and all
-   columns (ofks_lp_collect).
+   (features, a, t, w) for every `row_stride`-th row and all columns
+   (ofks_lp_collect): by default the energy-norm objective, which fits the
+   scale s node by node to minimize the quadratic model of T over s J g.
 2. Train: full-batch Adam on the device (ofks_lp_train), hand-written forward
    and backward kernels.
 3. Save the 193 weights and the 8 standardization constants as JSON.
@@ -38,7 +39,7 @@ def init_weights(seed: int) -> np.ndarray:
 
 
 def collect(seeds, kind: str = "c2", target_dofs: int = 200_000, iters: int = 60, row_stride: int = 64,
-            cap: int = 40_000_000, pcg_iters: int = 10, log=print):
+            cap: int = 40_000_000, pcg_iters: int = 10, objective: str = "energy", log=print):
     import torch
     sys.path.insert(0, os.path.dirname(HERE))
     import workloads as wl
@@ -57,7 +58,7 @@ def collect(seeds, kind: str = "c2", target_dofs: int = 200_000, iters: int = 60
         view = buf[count:]
         if view.shape[0] == 0:
             break
-        s.lp_collect(view, row_stride)
+        s.lp_collect(view, row_stride, objective)
         s.step(iters + 1)
         got = s.lp_collected()
         s.lp_collect(None, 0)
@@ -95,16 +96,19 @@ def main():
     ap.add_argument("--row-stride", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--objective", default="energy", choices=["energy", "euclid"])
+    ap.add_argument("--cap", type=float, default=4e7, help="sample capacity")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     a = ap.parse_args()
     lo, hi = (int(x) for x in a.seeds.split(":"))
     t = time.perf_counter()
-    S = collect(range(lo, hi), a.kind, a.target_dofs, a.iters, a.row_stride)
+    S = collect(range(lo, hi), a.kind, a.target_dofs, a.iters, a.row_stride, int(a.cap), objective=a.objective)
     t_collect = time.perf_counter() - t
     t = time.perf_counter()
     W, norm, losses = train(S, a.epochs, a.lr)
     t_train = time.perf_counter() - t
-    meta = dict(seeds=a.seeds, kind=a.kind, target_dofs=a.target_dofs, iters=a.iters, row_stride=a.row_stride,
+    meta = dict(seeds=a.seeds, kind=a.kind, objective=a.objective, target_dofs=a.target_dofs, iters=a.iters,
+                row_stride=a.row_stride,
                 samples=int(S.shape[0]), epochs=a.epochs, lr=a.lr, loss_first=float(losses[0]),
                 loss_last=float(losses[-1]), seconds_collect=t_collect, seconds_train=t_train)
     save(a.out, W, norm, meta)

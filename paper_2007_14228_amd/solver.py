@@ -262,14 +262,17 @@ class Solver:
             raise ValueError("weights must be 193 floats and norm 8 floats")
         self._check(self.lib.ofks_lp_set_weights(self.h, _np_ptr(w), _np_ptr(norm)))
 
-    def lp_collect(self, buf, row_stride: int):
-        """buf: device float32 tensor [cap, 8] (or None to stop)."""
+    def lp_collect(self, buf, row_stride: int, objective: str = "energy"):
+        """buf: device float32 tensor [cap, 8] (or None to stop); objective
+        "euclid" (0) or "energy" (1), see ofks_lp_collect."""
+        obj = {"euclid": 0, "energy": 1}[objective] if isinstance(objective, str) else int(objective)
         if buf is None:
-            self._check(self.lib.ofks_lp_collect(self.h, 0, ctypes.c_void_p(None), 0))
+            self._check(self.lib.ofks_lp_collect(self.h, 0, obj, ctypes.c_void_p(None), 0))
             return
         if buf.dim() != 2 or int(buf.shape[1]) != 8:
             raise ValueError("sample buffer must be [cap, 8]")
-        self._check(self.lib.ofks_lp_collect(self.h, int(row_stride), _dev_ptr(buf, "float32"), int(buf.shape[0])))
+        self._check(self.lib.ofks_lp_collect(self.h, int(row_stride), obj, _dev_ptr(buf, "float32"),
+                                             int(buf.shape[0])))
 
     def lp_collected(self) -> int:
         n = ctypes.c_int64()

@@ -70,3 +70,44 @@ def test_learned_form_with_untrained_network_still_converges():
     assert hist[-1].rel < 1e-9
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_dense_eigs.json")))
     assert abs(hist[-1].energy - sum(ref["eigenvalues"][: w.p])) < 1e-8
+
+
+def test_energy_samples_give_the_T_norm_error_for_a_constant_scale():
+    """For a constant scale s the energy-norm samples' loss differs from
+    ||s J g - T^-1 g||_T^2 (per-column weight included) by a term without s,
+    so both have the minimizer s* = (J g)^T g / (J g)^T T (J g); clamping only
+    drops the negative weights."""
+    import scipy.sparse.linalg as spla
+    w = wl.make_workload("c1")
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    lhd, bd, hd = prob.diag(0.5 * d.L), prob.diag(d.B), prob.diag(d.H)
+    rng = np.random.default_rng(11)
+    G = rng.standard_normal((d.n, 3))
+    lam = np.array([-0.6, 0.3, -2.5])
+    Ts = [d.csr(0.5 * d.L) - lam[l] * d.csr(d.B) if lam[l] < 0 else None for l in range(3)]
+    t = np.stack([spla.spsolve(Ts[l].tocsc(), G[:, l]) if Ts[l] is not None else G[:, l] for l in range(3)], axis=1)
+    a = mlp.jacobi(lhd, bd, lam) * G
+    u = np.stack([Ts[l] @ a[:, l] if Ts[l] is not None else G[:, l] for l in range(3)], axis=1)
+    S = mlp.samples(lhd, bd, hd, lam, G, t, u, "energy", clamp=False)
+    for l in range(3):
+        Tl = Ts[l] if Ts[l] is not None else None
+        scale = d.n / float(G[:, l] @ t[:, l])
+
+        def tnorm2(v):
+            return float(v @ (Tl @ v)) if Tl is not None else float(v @ v)
+
+        diffs, mags = [], []
+        for sc in (0.3, 0.9, 1.7, 4.0):
+            Lp = float(np.sum(S[:, l, 6] * (sc * S[:, l, 4] - S[:, l, 5]) ** 2))
+            diffs.append(Lp - scale * tnorm2(sc * a[:, l] - t[:, l]))
+            mags.append(abs(Lp))
+        assert np.ptp(diffs) <= 1e-10 * max(mags)
+        s_star = float(a[:, l] @ G[:, l]) / tnorm2(a[:, l])
+        s_fit = float(np.sum(S[:, l, 6] * S[:, l, 5]) / np.sum(S[:, l, 6]))
+        assert abs(s_fit - s_star) <= 1e-10 * abs(s_star)
+    Sc = mlp.samples(lhd, bd, hd, lam, G, t, u, "energy")
+    assert np.all(Sc[:, :, 6] >= 0)
+    assert np.array_equal(Sc[:, :, 6], np.maximum(S[:, :, 6], 0.0))
+    # the identity-branch column: T = I, J = 1, so every target is 1
+    assert np.allclose(S[:, 1, 5], 1.0)
