@@ -268,6 +268,106 @@ template <typename T> __device__ __forceinline__ int mfma_row(int lk, int i) {
     return sizeof(T) == 8 ? lk + 4 * i : 4 * lk + i;
 }
 
+// Gram on the matrix cores: the same split-K partial tiles as k_gram, tile
+// TM x TN = 128 x 128, the 4 waves as 2 x 2, each owning 64 x 64 (4 x 4
+// MFMA tiles).  Rows of X and Y are staged through a double-buffered LDS in
+// chunks of 16, the next chunk's loads in flight while the current one is
+// multiplied (one barrier per chunk).  Here the A operand is X^T (a = column
+// of X, k = row) and B is Y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int p, int64_t rows_per_split,
+                                                  const T *__restrict__ X, const T *__restrict__ BX,
+                                                  const T *__restrict__ HX, double *__restrict__ part) {
+    constexpr int TM = 128, TN = 128, KC = 16, PAD = 4;
+    constexpr int EX = KC * TM / 256, EY = KC * TN / 256;
+    using acc_t = typename mfma4<T>::type;
+    __shared__ T Xs[2][KC][TM + PAD];
+    __shared__ T Ys[2][KC][TN + PAD];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wy = w >> 1, wx = w & 1;
+    const int a0 = blockIdx.x * TM, c0 = blockIdx.y * TN;
+    const int64_t r_begin = (int64_t)blockIdx.z * rows_per_split;
+    const int64_t r_end = min(n, r_begin + rows_per_split);
+    const int p2 = 2 * p;
+    acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{T(0), T(0), T(0), T(0)};
+    T xr[EX], yr[EY];
+    auto gload = [&](int64_t r0) {
+#pragma unroll
+        for (int j = 0; j < EX; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int kk = e / TM, cc = e % TM;
+            const int64_t r = r0 + kk;
+            const int a = a0 + cc;
+            xr[j] = (r < r_end && a < p) ? X[r * p + a] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < EY; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int kk = e / TN, cc = e % TN;
+            const int64_t r = r0 + kk;
+            const int c = c0 + cc;
+            T v = T(0);
+            if (r < r_end && c < p2) v = c < p ? BX[r * p + c] : HX[r * p + (c - p)];
+            yr[j] = v;
+        }
+    };
+    auto lstore = [&](int b) {
+#pragma unroll
+        for (int j = 0; j < EX; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            Xs[b][e / TM][e % TM] = xr[j];
+        }
+#pragma unroll
+        for (int j = 0; j < EY; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            Ys[b][e / TN][e % TN] = yr[j];
+        }
+    };
+    int buf = 0;
+    if (r_begin < r_end) {
+        gload(r_begin);
+        lstore(0);
+    }
+    __syncthreads();
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
+        const bool more = r0 + KC < r_end;
+        if (more) gload(r0 + KC);
+#pragma unroll
+        for (int s4 = 0; s4 < KC / 4; ++s4) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = Xs[buf][4 * s4 + lk][64 * wy + 16 * i + li];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Ys[buf][4 * s4 + lk][64 * wx + 16 * j + li];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
+        }
+        if (more) lstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    double *out = part + (int64_t)blockIdx.z * p * p2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + 64 * wx + 16 * j + li;
+            if (c >= p2) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int a = a0 + 64 * wy + 16 * i + mfma_row<T>(lk, q);
+                if (a < p) out[(int64_t)a * p2 + c] = (double)acc[i][j][q];
+            }
+        }
+}
+
 template <typename T, int NTW, int EPI>
 __global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A,
                                                      const T *__restrict__ sa, const T *__restrict__ M,
@@ -766,7 +866,7 @@ hipError_t launch_gram(hipStream_t s, int64_t n, int p, const GramPlan &g, const
     if (g.mt == 1) hipLaunchKernelGGL((k_gram<T, ACC, 1, 2>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
     else if (g.mt == 2) hipLaunchKernelGGL((k_gram<T, ACC, 2, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
     else if (g.mt == 4) hipLaunchKernelGGL((k_gram<T, ACC, 4, 4>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
-    else hipLaunchKernelGGL((k_gram<T, ACC, 8, 8>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
+    else hipLaunchKernelGGL((k_gram_mfma<T>), grid, dim3(256), 0, s, n, p, rps, X, BX, HX, part);
     return hipGetLastError();
 }
 
