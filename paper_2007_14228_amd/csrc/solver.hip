@@ -226,6 +226,8 @@ struct ofks_ctx {
     double *g2 = nullptr, *tw = nullptr;
     float *lp_buf = nullptr;     // training-sample collection
     int64_t lp_cap = 0, lp_count = 0, lp_stride = 0;
+    double f32_best = 0.0;       // FP32 phase: lowest residual so far and its iteration
+    int f32_best_k = 0;
     int lp_objective = 0;        // 0: Euclidean imitation of T^-1 g, 1: energy-norm imitation
     void *lp_u = nullptr;        // T (J G) for the energy-norm samples
     size_t lp_u_bytes = 0;
@@ -1333,6 +1335,8 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     c->ehist.clear();
     c->lp_hold = 0;
     c->last_kind = -1;
+    c->f32_best = INFINITY;
+    c->f32_best_k = 0;
     return sync(c);
 }
 
@@ -1356,9 +1360,17 @@ int ofks_step(ofks_ctx *c, int32_t max_steps, ofks_iter_stats *stats, int32_t *n
             c->done = true;
             break;
         }
-        if (c->prec == OFKS_F32 && c->prm.refine_tol > 0.0 && st.rel < c->prm.refine_tol) {
-            rc = promote_to_f64(c);
-            if (rc < 0) break;
+        if (c->prec == OFKS_F32 && c->prm.refine_tol > 0.0) {
+            // switch to FP64 below refine_tol, or when the FP32 phase has not
+            // lowered its best residual for 50 iterations (its rounding floor)
+            if (st.rel < c->f32_best) {
+                c->f32_best = st.rel;
+                c->f32_best_k = st.k;
+            }
+            if (st.rel < c->prm.refine_tol || st.k - c->f32_best_k > 50) {
+                rc = promote_to_f64(c);
+                if (rc < 0) break;
+            }
         }
     }
     if (n_stats) *n_stats = ns;

@@ -286,6 +286,24 @@ def test_mixed_precision_with_fp64_refinement(c1):
     assert abs(stats[-1]["energy"] - ref.sum()) < 1e-6
 
 
+def test_fp32_stall_switches_to_fp64(c1):
+    """An FP32 phase asked for a residual below its rounding floor stops
+    improving; after 50 iterations without a new best it switches to FP64 and
+    the run converges."""
+    w, d = c1
+    print("[gpu] fp32 stall", flush=True)
+    s = _solver_for(w)
+    s.set_params(beta=w.beta, tol=1e-10, max_iter=4000, precond="paper", precision="f32", refine_tol=1e-14)
+    s.set_x0(_dev(wl.random_block(0, d.n, w.p)), orthonormalize=True)
+    stats, done, _ = s.step(4000)
+    assert done and stats[-1]["rel"] < 1e-10
+    prec = [x["precision"] for x in stats]
+    k64 = prec.index(0)
+    assert k64 > 50 and all(q == 1 for q in prec[:k64]) and all(q == 0 for q in prec[k64:])
+    ref = np.array(json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p])
+    assert abs(stats[-1]["energy"] - ref.sum()) < 1e-8
+
+
 # ----------------------------------------------------------------------------
 # errors are reported, not faulted
 # ----------------------------------------------------------------------------
