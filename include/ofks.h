@@ -79,7 +79,8 @@ typedef struct {
     int32_t fallback_hold;  /* learned form: iterations on the paper preconditioner after a fallback */
     int32_t fallback_rule;  /* learned form: a fallback when E^k exceeds 0: the minimum, 1: the maximum
                                of the previous fallback_window energies */
-    int32_t reserved[4];
+    int32_t use_graphs;     /* 1: replay launch-bound inner loops (Hartree CG) as HIP graphs; 0: launch eagerly */
+    int32_t reserved[3];
 } ofks_params;
 
 typedef struct {

@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
         ("fallback_window", _c_int32),
         ("fallback_hold", _c_int32),
         ("fallback_rule", _c_int32),
-        ("reserved", _c_int32 * 4),
+        ("use_graphs", _c_int32),
+        ("reserved", _c_int32 * 3),
     ]
 
 

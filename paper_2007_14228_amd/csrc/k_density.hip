@@ -187,26 +187,40 @@ __global__ __launch_bounds__(256) void k_cg_reduce3(int nb, const double *__rest
     if (threadIdx.x == 0) { sc[0] = r[0][0]; sc[1] = r[1][0]; sc[2] = r[2][0]; }
 }
 
-// alpha = rz / dq from the SpMV partials
-__global__ __launch_bounds__(256) void k_cg_alpha(int nb, const double *__restrict__ part, double *__restrict__ sc) {
+// Fixed-order sum of part[k * stride + off], k < nb, computed identically by
+// every block that calls it (all 256 threads; the result is returned to all).
+__device__ __forceinline__ double block_fixed_sum(int nb, int stride, int off, const double *__restrict__ part) {
     __shared__ double r[256];
-    double a = 0;
-    for (int k = threadIdx.x; k < nb; k += 256) a += part[k];
+    double a = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) a += part[(int64_t)k * stride + off];
     r[threadIdx.x] = a;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) { sc[5] = r[0]; sc[3] = r[0] > 0.0 ? sc[0] / r[0] : 0.0; }
+    const double v = r[0];
+    __syncthreads();
+    return v;
 }
 
-// x += alpha d ; r -= alpha q ; partials rz_new, rr
-__global__ __launch_bounds__(256) void k_cg_xr(int64_t n, const double *__restrict__ sc,
-                                              const double *__restrict__ d, const double *__restrict__ q,
-                                              const double *__restrict__ dg, double *__restrict__ x,
-                                              double *__restrict__ r, double *__restrict__ part) {
-    const double alpha = sc[3];
+// One CG iteration after q = L d (partials dq[nb]): every block forms
+// alpha = rz / <d, q> from the partials itself (same fixed order in every
+// block), then x += alpha d, r -= alpha q, partials of <r, z> and <r, r>.
+// rz is read from sc[0] or sc[6] by iteration parity (k_cg_dir writes the
+// other slot, so no block overwrites a value another block still reads).
+__global__ __launch_bounds__(256) void k_cg_xr(int64_t n, int parity, double *__restrict__ sc, int nb,
+                                              const double *__restrict__ dq, const double *__restrict__ d,
+                                              const double *__restrict__ q, const double *__restrict__ dg,
+                                              double *__restrict__ x, double *__restrict__ r,
+                                              double *__restrict__ part) {
+    const double dqs = block_fixed_sum(nb, 1, 0, dq);
+    const double rz_old = sc[parity ? 6 : 0];
+    const double alpha = dqs > 0.0 ? rz_old / dqs : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[3] = alpha;
+        sc[5] = dqs;
+    }
     double rz = 0.0, rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] = fma(alpha, d[i], x[i]);
@@ -218,27 +232,21 @@ __global__ __launch_bounds__(256) void k_cg_xr(int64_t n, const double *__restri
     block_sum2(rz, rr, &part[3 * blockIdx.x], &part[3 * blockIdx.x + 1]);
 }
 
-// beta = rz_new / rz ; rz = rz_new ; rr stored
-__global__ __launch_bounds__(256) void k_cg_beta(int nb, const double *__restrict__ part, double *__restrict__ sc) {
-    __shared__ double r[2][256];
-    double a = 0, b = 0;
-    for (int k = threadIdx.x; k < nb; k += 256) { a += part[3 * k]; b += part[3 * k + 1]; }
-    r[0][threadIdx.x] = a; r[1][threadIdx.x] = b;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) { r[0][threadIdx.x] += r[0][threadIdx.x + w]; r[1][threadIdx.x] += r[1][threadIdx.x + w]; }
-        __syncthreads();
+// beta = <r, z>_new / <r, z>_old from the k_cg_xr partials (formed in every
+// block), d = z + beta d; block 0 stores <r, z>_new in the other parity slot
+// and <r, r> in sc[1] (the host's convergence check).
+__global__ __launch_bounds__(256) void k_cg_dir(int64_t n, int parity, double *__restrict__ sc, int nb,
+                                               const double *__restrict__ part, const double *__restrict__ r,
+                                               const double *__restrict__ dg, double *__restrict__ d) {
+    const double rz_new = block_fixed_sum(nb, 3, 0, part);
+    const double rr = block_fixed_sum(nb, 3, 1, part);
+    const double rz_old = sc[parity ? 6 : 0];
+    const double beta = rz_old > 0.0 ? rz_new / rz_old : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[parity ? 0 : 6] = rz_new;
+        sc[1] = rr;
+        sc[4] = beta;
     }
-    if (threadIdx.x == 0) {
-        sc[4] = sc[0] > 0.0 ? r[0][0] / sc[0] : 0.0;
-        sc[0] = r[0][0];
-        sc[1] = r[1][0];
-    }
-}
-
-__global__ void k_cg_dir(int64_t n, const double *__restrict__ sc, const double *__restrict__ r,
-                         const double *__restrict__ dg, double *__restrict__ d) {
-    const double beta = sc[4];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         d[i] = fma(beta, d[i], r[i] / dg[i]);
 }
@@ -293,19 +301,15 @@ hipError_t launch_cg_start(hipStream_t s, int grid, int64_t n, double scale, con
     hipLaunchKernelGGL(k_cg_reduce3, dim3(1), dim3(256), 0, s, grid, part, sc);
     return hipGetLastError();
 }
-hipError_t launch_cg_alpha(hipStream_t s, int nb, const double *part, double *sc) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, nb, part, sc);
+hipError_t launch_cg_xr(hipStream_t s, int grid, int64_t n, int parity, double *sc, const double *dq,
+                        const double *d, const double *q, const double *dg, double *x, double *r, double *part) {
+    hipLaunchKernelGGL(k_cg_xr, dim3(grid), dim3(256), 0, s, n, parity, sc, grid, dq, d, q, dg, x, r, part);
     return hipGetLastError();
 }
-hipError_t launch_cg_xr(hipStream_t s, int grid, int64_t n, const double *sc, const double *d, const double *q,
-                        const double *dg, double *x, double *r, double *part) {
-    hipLaunchKernelGGL(k_cg_xr, dim3(grid), dim3(256), 0, s, n, sc, d, q, dg, x, r, part);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, grid, part, (double *)sc);
-    return hipGetLastError();
-}
-hipError_t launch_cg_dir(hipStream_t s, int grid, int64_t n, const double *sc, const double *r, const double *dg,
-                         double *d) {
-    hipLaunchKernelGGL(k_cg_dir, dim3(grid), dim3(256), 0, s, n, sc, r, dg, d);
+
+hipError_t launch_cg_dir(hipStream_t s, int grid, int64_t n, int parity, double *sc, const double *part,
+                         const double *r, const double *dg, double *d) {
+    hipLaunchKernelGGL(k_cg_dir, dim3(grid), dim3(256), 0, s, n, parity, sc, grid, part, r, dg, d);
     return hipGetLastError();
 }
 hipError_t launch_dot(hipStream_t s, int grid, int64_t n, const double *a, const double *b, double *part) {

@@ -402,8 +402,11 @@ template <typename K> int resident_grid(K kernel, int cap) {
     return cached < cap ? cached : cap;
 }
 
-// Scalar SpMV with the dot <d, A d> fused (Hartree CG); persistent grid,
-// one lane per row, per-block partial written to part[block].
+// SpMV with the dot <d, A d> fused (Hartree CG); persistent grid, 16 lanes
+// per row (P1 rows hold about 15 entries): each lane takes every 16th entry
+// of the row with coalesced loads, the 16 partial sums are combined by
+// shuffles in a fixed order, and the group's first lane writes q_i and
+// accumulates d_i q_i.  Per-block partial written to part[block].
 __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__restrict__ rp,
                                                  const int32_t *__restrict__ col,
                                                  const double *__restrict__ a,
@@ -411,13 +414,22 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
                                                  double *__restrict__ q,
                                                  double *__restrict__ part) {
     __shared__ double red[256];
+    const int sub = threadIdx.x & 15;
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rows_per_pass = (int64_t)gridDim.x * (blockDim.x / 16);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 16) + (threadIdx.x >> 4); i - (threadIdx.x >> 4) < n;
+         i += rows_per_pass) {
         double acc = 0.0;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) acc = fma(a[e], d[col[e]], acc);
-        q[i] = acc;
-        s = fma(d[i], acc, s);
+        if (i < n) {
+            const int64_t e1 = rp[i + 1];
+            for (int64_t e = rp[i] + sub; e < e1; e += 16) acc = fma(a[e], d[col[e]], acc);
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+        if (sub == 0 && i < n) {
+            q[i] = acc;
+            s = fma(d[i], acc, s);
+        }
     }
     red[threadIdx.x] = s;
     __syncthreads();

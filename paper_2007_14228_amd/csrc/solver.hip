@@ -132,10 +132,10 @@ hipError_t launch_veff(hipStream_t, int64_t, const int32_t *, const int32_t *, c
                        const double *, double *);
 hipError_t launch_cg_start(hipStream_t, int, int64_t, double, const double *, const double *, const double *,
                            double *, double *, double *, double *);
-hipError_t launch_cg_alpha(hipStream_t, int, const double *, double *);
-hipError_t launch_cg_xr(hipStream_t, int, int64_t, const double *, const double *, const double *,
+hipError_t launch_cg_xr(hipStream_t, int, int64_t, int, double *, const double *, const double *, const double *,
                         const double *, double *, double *, double *);
-hipError_t launch_cg_dir(hipStream_t, int, int64_t, const double *, const double *, const double *, double *);
+hipError_t launch_cg_dir(hipStream_t, int, int64_t, int, double *, const double *, const double *, const double *,
+                         double *);
 hipError_t launch_dot(hipStream_t, int, int64_t, const double *, const double *, double *);
 }  // namespace ofks
 
@@ -193,7 +193,8 @@ struct ofks_ctx {
 
     // SCF work
     double *rho_q = nullptr, *eps_q = nullptr, *vxc_q = nullptr, *veff_q = nullptr, *bvec = nullptr,
-           *U = nullptr, *cg_r = nullptr, *cg_d = nullptr, *cg_q = nullptr, *cg_sc = nullptr;
+           *U = nullptr, *cg_r = nullptr, *cg_d = nullptr, *cg_q = nullptr, *cg_sc = nullptr,
+           *cg_part = nullptr;   // Hartree CG partial sums (fixed: the captured graph holds the pointer)
     double scf_parts[4] = {0, 0, 0, 0};  // int rho, int eps rho, int vxc rho, U.b/2
 
     // iteration
@@ -226,6 +227,7 @@ struct ofks_ctx {
     double *g2 = nullptr, *tw = nullptr;
     float *lp_buf = nullptr;     // training-sample collection
     int64_t lp_cap = 0, lp_count = 0, lp_stride = 0;
+    hipGraphExec_t cg_graph = nullptr;   // 10 Hartree CG iterations, captured once per system
     double f32_best = 0.0;       // FP32 phase: lowest residual so far and its iteration
     int f32_best_k = 0;
     int lp_objective = 0;        // 0: Euclidean imitation of T^-1 g, 1: energy-norm imitation
@@ -498,31 +500,70 @@ template <typename T> int coldot(ofks_ctx *c, const T *A, const T *B, std::vecto
 // ---------------------------------------------------------------------------
 // SCF: H(X) for X = Xs .* dinv (Section 2.2)
 // ---------------------------------------------------------------------------
+// Hartree CG grid: enough 256-thread blocks to fill the device (the vectors
+// are short, so the kernels are latency-bound); the fused reductions sum one
+// partial per block.
+constexpr int CG_BLOCKS = 2048;
+
+void drop_cg_graph(ofks_ctx *c) {
+    if (c->cg_graph) (void)hipGraphExecDestroy(c->cg_graph);
+    c->cg_graph = nullptr;
+}
+
 int poisson(ofks_ctx *c) {
     const int64_t n = c->n;
-    const int g = 512;
-    CHK(ensure_part(c, (size_t)3 * g));
+    const int g = CG_BLOCKS;                    // blocks; partials: <d, q> then 3-wide update sums
+    double *dqp = c->cg_part, *xrp = c->cg_part + g;
     {
         Scope sc(c, "poisson");
-        HIPCHK(launch_spmv_dot(c->stream, g, n, c->rp, c->col, c->Lv, c->U, c->cg_q, c->part));
+        HIPCHK(launch_spmv_dot(c->stream, g, n, c->rp, c->col, c->Lv, c->U, c->cg_q, dqp));
         // Jacobi preconditioner diag(L/2): a constant multiple of diag(L) leaves the CG iterates unchanged
-        HIPCHK(launch_cg_start(c->stream, g, n, 4.0 * M_PI, c->bvec, c->cg_q, c->lhd, c->cg_r, c->cg_d, c->part,
+        HIPCHK(launch_cg_start(c->stream, g, n, 4.0 * M_PI, c->bvec, c->cg_q, c->lhd, c->cg_r, c->cg_d, xrp,
                                c->cg_sc));
     }
     std::vector<double> sc;
     CHK(download(c, sc, c->cg_sc, 3));
     double rr = sc[1], bb = sc[2];
     const double tol2 = c->prm.poisson_rtol * c->prm.poisson_rtol * bb;
+    // ten CG iterations (30 launches; an even count, so <r, z> ends in sc[0]
+    // again), replayed as one graph when allowed
+    auto chunk = [&](hipStream_t s) -> hipError_t {
+        for (int j = 0; j < 10; ++j) {
+            hipError_t e;
+            if ((e = launch_spmv_dot(s, g, n, c->rp, c->col, c->Lv, c->cg_d, c->cg_q, dqp)) != hipSuccess) return e;
+            if ((e = launch_cg_xr(s, g, n, j & 1, c->cg_sc, dqp, c->cg_d, c->cg_q, c->lhd, c->U, c->cg_r, xrp)) !=
+                hipSuccess)
+                return e;
+            if ((e = launch_cg_dir(s, g, n, j & 1, c->cg_sc, xrp, c->cg_r, c->lhd, c->cg_d)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (c->prm.use_graphs && !c->cg_graph) {
+        // captured on a private stream (the context's stream may be the null
+        // stream, which cannot be captured); every node is a kernel launch
+        hipStream_t cs = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t el = chunk(cs);
+            e = hipStreamEndCapture(cs, &gr);
+            if (e == hipSuccess) e = el;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->cg_graph, gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            c->cg_graph = nullptr;
+            return fail(c, OFKS_EHIP, "Hartree CG graph capture: %s", hipGetErrorString(e));
+        }
+    }
     int it = 0;
     while (rr > tol2 && it < c->prm.poisson_max_iter) {
         {
             Scope s2(c, "poisson");
-            for (int j = 0; j < 10; ++j) {
-                HIPCHK(launch_spmv_dot(c->stream, g, n, c->rp, c->col, c->Lv, c->cg_d, c->cg_q, c->part));
-                HIPCHK(launch_cg_alpha(c->stream, g, c->part, c->cg_sc));
-                HIPCHK(launch_cg_xr(c->stream, g, n, c->cg_sc, c->cg_d, c->cg_q, c->lhd, c->U, c->cg_r, c->part));
-                HIPCHK(launch_cg_dir(c->stream, g, n, c->cg_sc, c->cg_r, c->lhd, c->cg_d));
-            }
+            if (c->prm.use_graphs) HIPCHK(hipGraphLaunch(c->cg_graph, c->stream));
+            else HIPCHK(chunk(c->stream));
         }
         it += 10;
         CHK(download(c, sc, c->cg_sc, 2));
@@ -931,6 +972,7 @@ int alloc_system_common(ofks_ctx *c) {
 }
 
 void free_system(ofks_ctx *c) {
+    drop_cg_graph(c);
     dfree(c, c->rp);
     dfree(c, c->col);
     dfree(c, c->Lv);
@@ -978,6 +1020,7 @@ void ofks_default_params(ofks_params *p) {
     p->fallback_window = 5;
     p->fallback_hold = 20;
     p->fallback_rule = 0;
+    p->use_graphs = 1;
 }
 
 int ofks_create(ofks_ctx **out, void *hip_stream) {
@@ -996,6 +1039,7 @@ int ofks_create(ofks_ctx **out, void *hip_stream) {
 int ofks_destroy(ofks_ctx *c) {
     if (!c) return OFKS_OK;
     (void)hipStreamSynchronize(c->stream);
+    drop_cg_graph(c);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->hbuf) (void)hipHostFree(c->hbuf);
@@ -1151,7 +1195,8 @@ int ofks_assemble(ofks_ctx *c) {
     dfree(c, errd);
     dfree(c, cursor);
     dfree(c, rowcnt);
-    // SCF work arrays
+    // SCF work arrays (the CG graph holds pointers to some of them)
+    drop_cg_graph(c);
     dfree(c, c->rho_q);
     dfree(c, c->eps_q);
     dfree(c, c->vxc_q);
@@ -1162,6 +1207,7 @@ int ofks_assemble(ofks_ctx *c) {
     dfree(c, c->cg_d);
     dfree(c, c->cg_q);
     dfree(c, c->cg_sc);
+    dfree(c, c->cg_part);
     CHK(dalloc(c, &c->rho_q, 4 * nt));
     CHK(dalloc(c, &c->eps_q, 4 * nt));
     CHK(dalloc(c, &c->vxc_q, 4 * nt));
@@ -1172,6 +1218,7 @@ int ofks_assemble(ofks_ctx *c) {
     CHK(dalloc(c, &c->cg_d, n));
     CHK(dalloc(c, &c->cg_q, n));
     CHK(dalloc(c, &c->cg_sc, 8));
+    CHK(dalloc(c, &c->cg_part, 4 * CG_BLOCKS));
     HIPCHK(hipMemsetAsync(c->U, 0, n * sizeof(double), s));
     c->has_system = true;
     c->assembled = true;

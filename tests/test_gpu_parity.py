@@ -251,6 +251,23 @@ def test_density_xc_hartree_and_hamiltonian(lih):
     assert _relerr(g["H"], Hval) < 1e-11
 
 
+def test_hartree_graph_replays_match_eager_launches(lih):
+    """The Hartree CG replayed as a captured graph gives bit-identical
+    potentials to eager launches, over consecutive solves (each many replays,
+    with host synchronization between them)."""
+    w, d = lih
+    print("[gpu] hartree graph vs eager", flush=True)
+    prob = scf.KSProblem(d, w.Z, w.R)
+    Xs = [pcal.chol_gs(prob, wl.random_block(40 + k, d.n, 2)) for k in range(3)]
+    Us = {}
+    for use in (0, 1):
+        s = _solver_for(w)
+        s.set_params(use_graphs=use)
+        Us[use] = [_host(s.build_hamiltonian(_dev(X))["U"]) for X in Xs]
+    for a, b in zip(Us[0], Us[1]):
+        assert np.array_equal(a, b)
+
+
 def test_scf_pcal_energy_matches_the_oracle(lih):
     w, d = lih
     print("[gpu] scf pcal", flush=True)
