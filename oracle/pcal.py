@@ -198,7 +198,7 @@ def pcal(prob, X0: np.ndarray, params: Params,
         fea = float(np.linalg.norm(S - I))
         if kkt0 is None:
             kkt0 = kkt
-        rel = (kkt + fea) / kkt0
+        rel = (kkt + fea) / kkt0 if kkt0 > 0 else kkt + fea   # stationary start: absolute
         E = prob.energy(X, S, L0)
         hist.append(IterRecord(k, kkt, fea, rel, float("nan") if eta is None else eta, E))
         if callback is not None:

@@ -810,7 +810,9 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     CHK(download(c, r2, c->red, 1 + p));
     const double kkt = std::sqrt(std::max(0.0, r2[0]));
     if (c->kkt0 < 0) c->kkt0 = kkt;
-    const double rel = (kkt + fea) / c->kkt0;
+    // relative to kkt_0; a start that is already stationary (kkt_0 = 0) is
+    // judged by the absolute value
+    const double rel = c->kkt0 > 0.0 ? (kkt + fea) / c->kkt0 : kkt + fea;
     c->last_kkt = kkt;
     c->last_fea = fea;
     c->last_rel = rel;

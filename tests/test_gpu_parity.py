@@ -339,3 +339,45 @@ def test_invalid_calls_return_errors(c1):
         s.set_x0(_dev(np.zeros((d.n + 1, 2))))      # wrong row count, caught before the call
     with pytest.raises(OfksError):
         s.set_x0(_dev(np.zeros((d.n, 3))))          # V^T B V singular
+
+
+def test_degenerate_inputs(c1):
+    """Empty and degenerate inputs return errors, never faults; the smallest
+    real system (one interior DOF, p = 1) converges to H_00 / B_00."""
+    import ctypes
+    from paper_2007_14228_amd import OfksError, Solver
+    w, d = c1
+    print("[gpu] degenerate inputs", flush=True)
+    s = _solver_for(w)
+    s.set_params()
+    X = _dev(wl.random_block(0, d.n, 3))
+    # p = 0 and p > 1024 through the C ABI directly (the binding rejects them earlier)
+    assert s.lib.ofks_set_x0(s.h, 0, ctypes.c_void_p(X.data_ptr()), 1) == -1
+    assert s.lib.ofks_set_x0(s.h, 1025, ctypes.c_void_p(X.data_ptr()), 1) == -1
+    with pytest.raises(OfksError):
+        s.step(1)                                           # no X0 yet
+    # a column with zero B-norm, taken as given
+    Z = wl.random_block(1, d.n, 3)
+    Z[:, 1] = 0.0
+    s.set_x0(_dev(Z), orthonormalize=False)
+    with pytest.raises(OfksError, match="zero B-norm"):
+        s.step(1)
+    # a mesh without interior nodes
+    ax = wl.uniform_axis(0.0, 1.0, 1)
+    s0 = Solver()
+    with pytest.raises(OfksError, match="no interior"):
+        s0.load_workload(wl.Workload("empty", wl.kuhn_mesh(ax, ax, ax), np.array([1.0]),
+                                     np.array([[0.5, 0.5, 0.5]]), p=1, beta=1.0, scf=False, seed=0))
+    # one interior DOF, one column
+    ax = wl.uniform_axis(-1.0, 1.0, 2)
+    w1 = wl.Workload("one", wl.kuhn_mesh(ax, ax, ax), np.array([1.0]), np.array([[0.3, 0.2, 0.1]]),
+                     p=1, beta=1.0, scf=False, seed=0)
+    d1 = fem.discretize(w1.mesh, w1.Z, w1.R)
+    assert d1.n == 1
+    s1 = _solver_for(w1)
+    s1.set_params(tol=1e-12, max_iter=50, precond="paper")
+    s1.set_x0(_dev(np.array([[2.0]])), orthonormalize=True)
+    st, done, _ = s1.step(50)
+    assert done
+    eig = s1.postprocess()
+    assert abs(eig[0] - d1.H[0] / d1.B[0]) <= 1e-14 * abs(d1.H[0] / d1.B[0])
