@@ -142,7 +142,8 @@ int ofks_set_params(ofks_ctx *ctx, const ofks_params *params);
 /* Starting block X0 (device f64[n*p]).  b_orthonormalize = 1 applies the
  * Cholesky-based Gram-Schmidt of Section 4.2 (X0 = V R^{-1}, R^T R = V^T B V);
  * 0 takes X0 as given.  Allocates the iteration blocks for this p.  Resets
- * the iteration counter.  ENOTSPD if V^T B V is not positive definite. */
+ * the iteration counter.  ENOTSPD if V^T B V is not positive definite;
+ * EZERONORM if a column taken as given has zero B-norm. */
 int ofks_set_x0(ofks_ctx *ctx, int32_t p, const double *dev_X0, int32_t b_orthonormalize);
 
 /* ---- main iteration (Algorithm PCAL) -------------------------------------- */

@@ -224,6 +224,8 @@ def pcal(prob, X0: np.ndarray, params: Params,
             if hold > 0 and not use_learned:
                 hold -= 1
         P = precondition(prob, G, lam_diag.copy(), params, kind)
+        if not np.any(P):
+            break                                  # P = 0: X is a fixed point of the update
         if k == 0:
             eta0 = params.eta0 if params.eta0 > 0 else float(np.linalg.norm(P) / np.linalg.norm(X))
             eta = eta0

@@ -912,6 +912,13 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     HIPCHK(launch_colsum(c->stream, c->grid, 5, c->part, c->red));
     std::vector<double> s5;
     CHK(download(c, s5, c->red, 5));
+    if (s5[3] == 0.0) {
+        // P = 0: X is a fixed point of the update (a stationary start, e.g. a
+        // single DOF); nothing further to do
+        *stop = true;
+        if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return OFKS_OK;
+    }
     if (!c->have_prev) {
         if (c->eta0 <= 0.0) c->eta0 = c->prm.eta0 > 0 ? c->prm.eta0 : std::sqrt(s5[3]) / std::sqrt(s5[4]);
         if (c->eta <= 0.0) c->eta = c->eta0;
@@ -1364,6 +1371,13 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
         HIPCHK(launch_rowgemm<double>(c->stream, EPI_PLAIN, c->n, p, p, c->gemm_rows, B.Xt, B.dinv, B.CC, B.HX, ga,
                                       nullptr));
         std::swap(B.Xt, B.HX);
+    } else {
+        // a block taken as given must have no column of zero B-norm
+        HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, B.Xt, B.BX, nullptr, 1));
+        std::vector<double> bn;
+        CHK(coldot<double>(c, B.Xt, B.BX, bn));
+        for (int i = 0; i < p; ++i)
+            if (!(bn[i] > 0.0)) return fail(c, OFKS_EZERONORM, "set_x0: column %d has zero B-norm", i);
     }
     if (c->prec == OFKS_F32) {
         if (!c->hb32) CHK(ensure_f32_matrices(c));

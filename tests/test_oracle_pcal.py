@@ -169,3 +169,19 @@ def test_bb_rules_on_a_quadratic():
         assert abs(pcal.bb_eta(rule, 3, s, 7.5 * s, 1.0, 1.0) - 7.5) < 1e-12
     # non-finite or zero curvature keeps the previous value
     assert pcal.bb_eta("bb2", 3, s, 0 * s, 2.0, 1.0) == 2.0
+
+
+def test_single_dof_stops_at_the_exact_eigenvalue():
+    """One interior DOF: any normalized start is the eigenvector, the
+    preconditioned gradient vanishes, the iteration stops at once and the
+    Rayleigh-Ritz value is H_00 / B_00."""
+    ax = wl.uniform_axis(-1.0, 1.0, 2)
+    mesh = wl.kuhn_mesh(ax, ax, ax)
+    d = fem.discretize(mesh, np.array([1.0]), np.array([[0.3, 0.2, 0.1]]))
+    assert d.n == 1
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X, hist = pcal.pcal(prob, pcal.chol_gs(prob, np.array([[2.0]])),
+                        pcal.Params(tol=1e-12, max_iter=50, precond="paper"))
+    assert len(hist) == 1
+    lam, _ = pcal.rayleigh_ritz(prob, X)
+    assert abs(lam[0] - d.H[0] / d.B[0]) <= 1e-15 * abs(d.H[0] / d.B[0])
