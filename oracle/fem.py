@@ -145,6 +145,38 @@ def discretize(mesh, Z: np.ndarray, R: np.ndarray) -> Discretization:
     return disc
 
 
+def local_rows(mesh, Z: np.ndarray, R: np.ndarray, rows) -> dict:
+    """Rows of L, B and M_ext for the given interior DOFs, assembled from the
+    tetrahedra that touch them only, with the element formulas of discretize
+    (and, the tetrahedra taken in mesh order, the same summation order).  For
+    checks at sizes where assembling everything here would take too long.
+    Returns {row: (cols ascending, L, B, Mext)}."""
+    xyz = mesh.xyz
+    dof = dof_numbering(mesh.dirichlet)
+    n = int((dof >= 0).sum())
+    rows = np.unique(np.asarray(rows, dtype=np.int64))
+    nodes = np.flatnonzero(np.isin(dof, rows))
+    tets = mesh.tets[np.isin(mesh.tets, nodes).any(axis=1)].astype(np.int64)
+    vol, g = tet_geometry(xyz, tets)
+    Kloc = vol[:, None, None] * np.einsum("kad,kbd->kab", g, g)
+    Mloc = np.broadcast_to(vol[:, None, None] * (np.ones((4, 4)) + np.eye(4))[None] / 20.0, Kloc.shape)
+    w = vol[:, None] / 4.0 * external_potential(quad_points(xyz, tets), Z, R)
+    Vloc = np.einsum("kq,qa,qb->kab", w, BARY, BARY)
+    d = dof[tets]
+    r = np.repeat(d[:, :, None], 4, axis=2).ravel()
+    c = np.repeat(d[:, None, :], 4, axis=1).ravel()
+    keep = np.isin(r, rows) & (c >= 0)
+    keys = r[keep] * n + c[keep]
+    uk, inv = np.unique(keys, return_inverse=True)
+    vals = [np.bincount(inv, weights=v.ravel()[keep], minlength=len(uk)) for v in (Kloc, Mloc, Vloc)]
+    out = {}
+    ur = uk // n
+    for i in rows:
+        m = ur == i
+        out[int(i)] = (uk[m] % n, vals[0][m], vals[1][m], vals[2][m])
+    return out
+
+
 def nuclear_repulsion(Z: np.ndarray, R: np.ndarray) -> float:
     """E_nuc = sum_{j<k} Z_j Z_k / |R_j - R_k|  (Section 2.1)."""
     e = 0.0

@@ -378,17 +378,21 @@ template <typename T> const void *lbT(ofks_ctx *c);
 template <> const void *lbT<double>(ofks_ctx *c) { return c->lb; }
 template <> const void *lbT<float>(ofks_ctx *c) { return c->lb32; }
 
-template <typename T> int alloc_blocks(ofks_ctx *c) {
+// All iteration blocks, or (setup_only) just those the start block's
+// B-orthonormalization uses: X, HX, BX (an FP32 run converts and frees them).
+template <typename T> int alloc_blocks(ofks_ctx *c, bool setup_only = false) {
     Blocks<T> &b = blk<T>(c);
     const size_t np = (size_t)c->n * c->p;
     CHK(dalloc(c, &b.Xt, np));
-    CHK(dalloc(c, &b.Xp, np));
-    CHK(dalloc(c, &b.P, np));
-    CHK(dalloc(c, &b.Pp, np));
     CHK(dalloc(c, &b.HX, np));
     CHK(dalloc(c, &b.BX, np));
-    CHK(dalloc(c, &b.R, np));
-    CHK(dalloc(c, &b.D, np));
+    if (!setup_only) {
+        CHK(dalloc(c, &b.Xp, np));
+        CHK(dalloc(c, &b.P, np));
+        CHK(dalloc(c, &b.Pp, np));
+        CHK(dalloc(c, &b.R, np));
+        CHK(dalloc(c, &b.D, np));
+    }
     CHK(dalloc(c, &b.dinv, c->p));
     CHK(dalloc(c, &b.CC, (size_t)c->p * 2 * c->p));
     CHK(dalloc(c, &b.lam, c->p));
@@ -1349,7 +1353,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     CHK(dalloc(c, &c->g2, p));
     CHK(dalloc(c, &c->tw, p));
     CHK(ensure_part(c, partials_needed(c, p)));
-    CHK(alloc_blocks<double>(c));
+    CHK(alloc_blocks<double>(c, c->prec == OFKS_F32));   // an FP32 run needs only the setup blocks in FP64
     Blocks<double> &B = c->b64;
     HIPCHK(hipMemcpyAsync(B.Xt, X0, (size_t)c->n * p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (orth) {
@@ -1382,6 +1386,10 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     if (c->prec == OFKS_F32) {
         if (!c->hb32) CHK(ensure_f32_matrices(c));
         else CHK(ensure_f32_matrices(c));
+        // free the FP64 products before the FP32 blocks exist (peak: X0, X and the FP32 blocks)
+        CHK(sync(c));
+        dfree(c, B.HX);
+        dfree(c, B.BX);
         CHK(alloc_blocks<float>(c));
         HIPCHK(launch_convert<double, float>(c->stream, c->n * (int64_t)p, B.Xt, c->b32.Xt));
         CHK(sync(c));

@@ -72,7 +72,7 @@ def test_csr_pattern_bit_exact_and_values(which, c1, graded):
     assert _relerr(g["H"], d.H) < 1e-13
 
 
-@pytest.mark.parametrize("p", [1, 3, 4, 11, 16, 33, 64, 128, 130])
+@pytest.mark.parametrize("p", [1, 3, 4, 11, 16, 33, 64, 128, 130, 260, 512])
 def test_dual_spmm(p, graded):
     w, d = graded
     print(f"[gpu] spmm p={p}", flush=True)
@@ -83,7 +83,7 @@ def test_dual_spmm(p, graded):
     assert _relerr(_host(BX), native.spmm(d.row_ptr, d.col, d.B, X)) < 1e-12
 
 
-@pytest.mark.parametrize("p", [1, 4, 11, 33, 128])
+@pytest.mark.parametrize("p", [1, 4, 11, 33, 128, 260, 512])
 def test_gram(p, graded):
     w, d = graded
     print(f"[gpu] gram p={p}", flush=True)
@@ -95,7 +95,7 @@ def test_gram(p, graded):
     assert _relerr(L0, X.T @ HX) < 1e-12
 
 
-@pytest.mark.parametrize("p", [1, 5, 16, 128, 130])
+@pytest.mark.parametrize("p", [1, 5, 16, 128, 130, 512])
 def test_preconditioner_cg(p, graded):
     w, d = graded
     print(f"[gpu] precondition p={p}", flush=True)
@@ -140,7 +140,7 @@ def test_first_iterations_follow_the_oracle(precond, c1):
         assert abs(st[k - 1]["eta"] - hist[k].eta) <= 1e-9 * hist[k].eta
 
 
-@pytest.mark.parametrize("p", [40, 128, 130])
+@pytest.mark.parametrize("p", [40, 128, 130, 512])
 def test_first_iterations_follow_the_oracle_wide_blocks(p, c1):
     """Step parity at block widths where the row GEMM runs on the matrix cores
     (p = 130: a ragged last column tile), paper preconditioner, FP64."""
@@ -157,7 +157,7 @@ def test_first_iterations_follow_the_oracle_wide_blocks(p, c1):
         assert abs(a["energy"] - b.energy) <= 1e-11 * abs(b.energy)
 
 
-@pytest.mark.parametrize("p", [40, 130])
+@pytest.mark.parametrize("p", [40, 130, 512])
 def test_fp32_iterations_stay_close_to_the_oracle(p, c1):
     """The FP32 block path (FP32 matrix-core products) tracks the FP64 oracle
     over the first iterations to FP32 accuracy."""

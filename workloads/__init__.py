@@ -30,6 +30,7 @@ __all__ = [
     "kuhn_mesh",
     "sample_cluster",
     "random_block",
+    "random_block_chunks",
     "make_workload",
     "CONFIGS",
 ]
@@ -263,6 +264,15 @@ def random_block(seed: int, n: int, p: int) -> np.ndarray:
     """i.i.d. N(0,1) block, row-major n x p (a node's p values contiguous)."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n, p))
+
+
+def random_block_chunks(seed: int, n: int, p: int, chunk_rows: int = 1 << 18):
+    """The rows of random_block(seed, n, p) in consecutive chunks (r0, r1, rows),
+    for blocks too large to hold at once; the same numbers as one call."""
+    rng = np.random.default_rng(seed)
+    for r0 in range(0, n, chunk_rows):
+        r1 = min(n, r0 + chunk_rows)
+        yield r0, r1, rng.standard_normal((r1 - r0, p))
 
 
 # ----------------------------------------------------------------------------
