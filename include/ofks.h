@@ -80,7 +80,9 @@ typedef struct {
     int32_t fallback_rule;  /* learned form: a fallback when E^k exceeds 0: the minimum, 1: the maximum
                                of the previous fallback_window energies */
     int32_t use_graphs;     /* 1: replay launch-bound inner loops (Hartree CG) as HIP graphs; 0: launch eagerly */
-    int32_t reserved[3];
+    int32_t algorithm;      /* 0: PCAL (Algorithm PCAL: eq. lambda2 multiplier, column B-normalization);
+                               1: PLAM (Algorithm PLAM: Lambda = X^T H X (eq. multi), no normalization) */
+    int32_t reserved[2];
 } ofks_params;
 
 typedef struct {

@@ -53,6 +53,7 @@ class Params:
     fallback_window: int = 5
     fallback_hold: int = 20
     fallback_rule: str = "min"     # fall back when E^k exceeds the "min" or "max" of the window
+    algorithm: str = "pcal"        # "pcal" (Algorithm PCAL) | "plam" (Algorithm PLAM)
 
 
 @dataclasses.dataclass
@@ -177,7 +178,8 @@ def bb_eta(rule: str, k: int, s: np.ndarray, y: np.ndarray, eta_prev: float, eta
 
 def pcal(prob, X0: np.ndarray, params: Params,
          callback: Optional[Callable] = None, return_state: bool = False):
-    """Run PCAL from X0 (B-orthonormal).  Returns X^k and the per-iteration log."""
+    """Run PCAL (or PLAM, params.algorithm) from X0 (B-orthonormal).  Returns X^k
+    and the per-iteration log."""
     X = np.array(X0, dtype=np.float64, copy=True)
     p = X.shape[1]
     I = np.eye(p)
@@ -205,7 +207,8 @@ def pcal(prob, X0: np.ndarray, params: Params,
             callback(k, X, HX, BX, S, L0)
         if rel < params.tol or k == params.max_iter:
             break
-        Lam = multiplier(S, L0, params.beta)
+        # PLAM: Lambda = X^T H X (eq. multi); PCAL: eq. lambda2
+        Lam = L0 if params.algorithm == "plam" else multiplier(S, L0, params.beta)
         G = HX + BX @ (params.beta * (S - I) - Lam)
         lam_diag = np.diag(Lam) if params.precond_lambda == "lambda2" else np.diag(L0)
         kind = params.precond
@@ -235,6 +238,10 @@ def pcal(prob, X0: np.ndarray, params: Params,
             eta = bb_eta(params.step_rule, k, X - Xprev, P - Pprev, eta, eta0)
         last_kind = kind
         Xt = X - P / eta
+        if params.algorithm == "plam":             # eq. PLAM-main: no normalization
+            Xprev, Pprev = X, P
+            X = Xt
+            continue
         dn = np.sqrt(np.einsum("ij,ij->j", Xt, prob.bx(Xt)))
         Xprev, Pprev = X, P
         X = Xt / dn

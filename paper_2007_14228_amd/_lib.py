@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
         ("fallback_hold", _c_int32),
         ("fallback_rule", _c_int32),
         ("use_graphs", _c_int32),
-        ("reserved", _c_int32 * 3),
+        ("algorithm", _c_int32),
+        ("reserved", _c_int32 * 2),
     ]
 
 

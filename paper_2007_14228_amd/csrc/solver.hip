@@ -666,11 +666,12 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     const int64_t n = c->n;
     const auto t0 = std::chrono::steady_clock::now();
     const bool scf = c->prm.scf != 0;
+    const bool plam = c->prm.algorithm == 1;   // Algorithm PLAM: no column normalization, Lambda = X^T H X
 
     // [SCF] normalize and rebuild H(X^k)
     if (scf) {
         std::vector<double> dn(p, 1.0);
-        if (c->k > 0) {
+        if (c->k > 0 && !plam) {
             {
                 Scope sc(c, "spmm_dual");
                 HIPCHK(launch_spmm_pair<T>(c->stream, n, p, c->rp, c->col, hbT<T>(c), B.Xt, B.BX, nullptr, 1));
@@ -699,7 +700,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     std::vector<double> &dn = c->dinv_h;
     if (!scf) {
         dn.assign(p, 1.0);
-        if (c->k > 0)
+        if (c->k > 0 && !plam)
             for (int i = 0; i < p; ++i) {
                 if (!(St[i * p + i] > 0.0)) return fail(c, OFKS_EZERONORM, "column %d has zero B-norm", i);
                 dn[i] = 1.0 / std::sqrt(St[i * p + i]);
@@ -732,7 +733,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
             sl += S[i * p + k2] * L0[k2 * p + i];
             ss += S[i * p + k2] * (S[k2 * p + i] - (k2 == i ? 1.0 : 0.0));
         }
-        lam_diag[i] = L0[i * p + i] + (L0[i * p + i] - sl + beta * ss);
+        lam_diag[i] = plam ? L0[i * p + i] : L0[i * p + i] + (L0[i * p + i] - sl + beta * ss);
     }
     for (int a = 0; a < p; ++a)
         for (int b = 0; b < p; ++b) {
@@ -1034,6 +1035,7 @@ void ofks_default_params(ofks_params *p) {
     p->fallback_hold = 20;
     p->fallback_rule = 0;
     p->use_graphs = 1;
+    p->algorithm = 0;
 }
 
 int ofks_create(ofks_ctx **out, void *hip_stream) {
@@ -1319,7 +1321,7 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
     if (!(prm->beta >= 0.0) || !(prm->tol > 0.0) || prm->max_iter < 0 || prm->pcg_iters < 0 ||
         prm->precond < 0 || prm->precond > 2 || prm->step_rule < 0 || prm->step_rule > 4 ||
         (prm->precision != OFKS_F64 && prm->precision != OFKS_F32) || prm->fallback_rule < 0 ||
-        prm->fallback_rule > 1)
+        prm->fallback_rule > 1 || prm->algorithm < 0 || prm->algorithm > 1)
         return fail(c, OFKS_EINVAL, "set_params: invalid parameter");
     if (prm->precond == OFKS_PRECOND_PAPER && prm->pcg_iters < 1)
         return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs pcg_iters >= 1");

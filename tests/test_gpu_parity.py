@@ -140,6 +140,36 @@ def test_first_iterations_follow_the_oracle(precond, c1):
         assert abs(st[k - 1]["eta"] - hist[k].eta) <= 1e-9 * hist[k].eta
 
 
+@pytest.mark.parametrize("algorithm,precond,step_rule", [("plam", "none", "bb2"), ("plam", "paper", "bb2"),
+                                                         ("pcal", "paper", "bb1"), ("pcal", "paper", "abb1"),
+                                                         ("pcal", "paper", "abb2"), ("pcal", "none", "fixed")])
+def test_other_algorithms_and_step_rules_follow_the_oracle(algorithm, precond, step_rule, c1):
+    """Algorithm PLAM and the BB1/ABB/fixed step rules (Section 4.4): the first
+    iterations against the oracle's, then (PLAM) convergence to the dense
+    eigenvalues."""
+    w, d = c1
+    print(f"[gpu] {algorithm} {precond} {step_rule}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    prm = dict(beta=w.beta, precond=precond, step_rule=step_rule, algorithm=algorithm)
+    if step_rule == "fixed":
+        prm["eta0"] = 40.0
+    _, hist = pcal.pcal(prob, X0, pcal.Params(tol=1e-30, max_iter=6, **prm))
+    s = _solver_for(w)
+    st = _run_gpu(s, X0, 6, tol=1e-30, pcg_iters=10, energy_every=1, **prm)
+    assert len(st) == len(hist) == 7
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-10 * b.kkt
+        assert abs(a["energy"] - b.energy) <= 1e-11 * abs(b.energy)
+    if algorithm == "plam":
+        s.set_params(tol=1e-10, max_iter=3000, pcg_iters=10, **prm)
+        s.set_x0(_dev(X0), orthonormalize=False)
+        st, done, _ = s.step(3000)
+        assert done and st[-1]["rel"] < 1e-10
+        ref = np.array(json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p])
+        assert np.allclose(s.postprocess(), ref, rtol=1e-10, atol=0)
+
+
 @pytest.mark.parametrize("p", [40, 128, 130, 512])
 def test_first_iterations_follow_the_oracle_wide_blocks(p, c1):
     """Step parity at block widths where the row GEMM runs on the matrix cores

@@ -185,3 +185,20 @@ def test_single_dof_stops_at_the_exact_eigenvalue():
     assert len(hist) == 1
     lam, _ = pcal.rayleigh_ritz(prob, X)
     assert abs(lam[0] - d.H[0] / d.B[0]) <= 1e-15 * abs(d.H[0] / d.B[0])
+
+
+@pytest.mark.parametrize("precond", ["none", "paper"])
+def test_plam_reaches_the_dense_eigenvalues(precond):
+    """Algorithm PLAM (eq. multi multiplier, eq. PLAM-main step, no
+    normalization) converges on the uniform single-nucleus problem to the
+    dense LAPACK eigenvalues, and to a B-orthonormal block."""
+    w = wl.make_workload("c1")
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    X, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-10, max_iter=3000, precond=precond,
+                                              algorithm="plam"))
+    assert hist[-1].rel < 1e-10 and hist[-1].fea < 1e-10
+    lam, _ = pcal.rayleigh_ritz(prob, X)
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_dense_eigs.json")))["eigenvalues"]
+    assert np.allclose(lam, ref[: w.p], rtol=1e-10, atol=0)
