@@ -47,7 +47,8 @@ enum {
     OFKS_ECAPACITY = -4,      /* mesh exceeds a compiled-in bound */
     OFKS_ENONFINITE = -5,     /* NaN/Inf in a p x p quantity */
     OFKS_ENOTSPD = -6,        /* Gram matrix not positive definite */
-    OFKS_EZERONORM = -7       /* a column with zero B-norm */
+    OFKS_EZERONORM = -7,      /* a column with zero B-norm */
+    OFKS_EINTERNAL = -8       /* a host-side consistency check of the library's own data failed */
 };
 
 /* Preconditioner choice (eq. precondition-T and the learned form). */
@@ -82,7 +83,12 @@ typedef struct {
     int32_t use_graphs;     /* 1: replay launch-bound inner loops (Hartree CG) as HIP graphs; 0: launch eagerly */
     int32_t algorithm;      /* 0: PCAL (Algorithm PCAL: eq. lambda2 multiplier, column B-normalization);
                                1: PLAM (Algorithm PLAM: Lambda = X^T H X (eq. multi), no normalization) */
-    int32_t reserved[2];
+    int32_t spmm_mode;      /* sparse products: 0 auto (LDS-halo kernel for FP64 blocks with p >= 64,
+                               row-gather otherwise);
+                               1 row-gather kernel; 2 LDS-halo kernel (products then fail with OFKS_ESTATE
+                               if the matrix has a row with more than 64 entries or more distinct columns
+                               than the halo holds).  The kernels agree to rounding. */
+    int32_t reserved[1];
 } ofks_params;
 
 typedef struct {

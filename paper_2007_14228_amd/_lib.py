@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
         ("fallback_rule", _c_int32),
         ("use_graphs", _c_int32),
         ("algorithm", _c_int32),
-        ("reserved", _c_int32 * 2),
+        ("spmm_mode", _c_int32),
+        ("reserved", _c_int32 * 1),
     ]
 
 

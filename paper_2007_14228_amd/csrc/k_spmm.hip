@@ -441,6 +441,241 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 }
 
 // ---------------------------------------------------------------------------
+// LDS-halo SpMM.  Block b owns the consecutive rows [row0[b], row0[b+1]) (at
+// most HALO_RMAX, each with at most 64 entries) and their halo: the distinct
+// columns of those rows, halo[hoff[b] .. hoff[b+1]) in ascending order (at
+// most HALO_MAX rows of X).  lcol[e] is the halo slot of CSR entry e.
+// Wave v of the block takes rows row0[b] + v + 8 i; it loads their entries
+// (slot, weight pair) once, one entry per lane, and keeps them in registers.
+// For each 512-byte slice of the columns the block stages its halo rows of X
+// in LDS, then every wave forms its rows from LDS, broadcasting the entries
+// with readlane.  X is gathered from L2 about (halo size / rows) times instead
+// of once per nonzero, and consecutive blocks (one XCD's slab, in dispatch
+// order) share their halos in that XCD's L2.
+//  MODE 0: Y1 = A1 X and Y2 = A2 X (or, Y2 = NULL, A1 X or A2 X by sel).
+//  MODE 1: Y1 = Q = (A1 - lam_c A2) D on active columns (0 elsewhere), and
+//          part[b][c] = <D_c, Q_c> over the block's rows.
+// ---------------------------------------------------------------------------
+// Tunables: halo rows (LDS = HALO_MAX x 512 B), rows per block, waves per
+// block, and the waves per SIMD the register budget is cut for (set by how
+// many blocks the LDS admits per CU).
+#ifndef OFKS_HALO_MAX
+#define OFKS_HALO_MAX 160
+#endif
+#ifndef OFKS_HALO_RMAX
+#define OFKS_HALO_RMAX 64
+#endif
+#ifndef OFKS_HALO_WAVES
+#define OFKS_HALO_WAVES 8
+#endif
+#ifndef OFKS_HALO_WPE
+#define OFKS_HALO_WPE 4
+#endif
+constexpr int HALO_MAX = OFKS_HALO_MAX, HALO_RMAX = OFKS_HALO_RMAX, HALO_WAVES = OFKS_HALO_WAVES, HALO_EMAX = 64;
+constexpr int HALO_RPW = HALO_RMAX / HALO_WAVES;   // rows per wave
+static_assert(HALO_RMAX % HALO_WAVES == 0, "whole rows per wave");
+
+__device__ __forceinline__ double bcast(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bcast(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// the register cap keeps every block the LDS admits resident
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu(OFKS_HALO_WPE))) void k_spmm_halo(
+    int64_t nb, int p, const int64_t *__restrict__ row0, const int64_t *__restrict__ hoff,
+    const int32_t *__restrict__ halo, const int64_t *__restrict__ rp, const uint16_t *__restrict__ lcol,
+    const typename pair_t<T>::type *__restrict__ w, const T *__restrict__ X, T *__restrict__ Y1,
+    T *__restrict__ Y2, int sel, const T *__restrict__ lam, const uint8_t *__restrict__ active,
+    double *__restrict__ part) {
+    using P2 = typename pair_t<T>::type;
+    constexpr int CP = 512 / sizeof(T);   // columns per slice: 64 (f64) or 128 (f32)
+    constexpr int VW = 16 / sizeof(T);    // one 16-byte load
+    constexpr int LPC = CP / 64;          // columns per lane in a slice
+    constexpr int SEG = CP / VW;
+    __shared__ T Xs[HALO_MAX * CP];
+    // MODE 1 per-wave dot partials reuse the slice's LDS once it is consumed
+    static_assert(HALO_WAVES * CP * sizeof(double) <= sizeof(T) * HALO_MAX * CP, "partials fit in the slice");
+    double *red = reinterpret_cast<double *>(Xs);
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (b >= nb) {   // padding block of the XCD mapping: a zero partial row
+        if (MODE == 1)
+            for (int c = threadIdx.x; c < p; c += blockDim.x) part[b * p + c] = 0.0;
+        return;
+    }
+    const int64_t r0 = row0[b], r1 = row0[b + 1], h0 = hoff[b];
+    const int hn = (int)(hoff[b + 1] - h0);
+    // 16-byte loads need every row start 16-byte aligned
+    const bool vec = p % VW == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    // staging: thread t always moves 16-byte segment t % SEG of halo slots
+    // t / SEG + SST u; the slots' rows of X are looked up once per block
+    constexpr int SST = 64 * HALO_WAVES / SEG;
+    constexpr int SPT = (HALO_MAX + SST - 1) / SST;
+    static_assert((64 * HALO_WAVES) % SEG == 0, "whole slot rows per pass");
+    const int sg = threadIdx.x % SEG, ss = threadIdx.x / SEG;
+    // (slots past the halo re-read its last row, never stored; a halo can be
+    // empty only for a block of empty rows)
+    int hrow[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+        const int64_t hi = hn > 0 ? h0 + min(ss + SST * u, hn - 1) : 0;   // entry 0 is always allocated
+        hrow[u] = halo[hi];
+    }
+    // this wave's rows: entry k of row i sits in lane k (lanes past the row
+    // re-read entry 0, which every allocation holds, and are never used)
+    int len[HALO_RPW], off[HALO_RPW];
+    T wa[HALO_RPW], wb[HALO_RPW];
+#pragma unroll
+    for (int i = 0; i < HALO_RPW; ++i) {
+        const int64_t row = r0 + wave + HALO_WAVES * i;
+        const int64_t e0 = row < r1 ? rp[row] : 0;
+        len[i] = row < r1 ? (int)(rp[row + 1] - e0) : 0;
+        const int64_t e = lane < len[i] ? e0 + lane : 0;
+        const P2 ww = w[e];
+        off[i] = (int)lcol[e] * CP;
+        wa[i] = ww.x;
+        wb[i] = ww.y;
+    }
+    for (int c0 = 0; c0 < p; c0 += CP) {
+        const int c = c0 + sg * VW;
+        if (vec && c0 + CP <= p) {
+            // whole aligned slice: every load of the slice in flight before
+            // the first LDS write
+            T v[SPT][VW];
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) load_vec<T, VW>(X + (int64_t)hrow[u] * p + c, v[u]);
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                const int sl = ss + SST * u;
+                if (sl < hn) {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) Xs[sl * CP + sg * VW + j] = v[u][j];
+                }
+            }
+        } else {
+            // ragged last slice or unaligned rows: element loads, zeros past p
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                const int sl = ss + SST * u;
+                const T *src = X + (int64_t)hrow[u] * p + c;
+                if (sl < hn) {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) Xs[sl * CP + sg * VW + j] = c + j < p ? src[j] : T(0);
+                }
+            }
+        }
+        __syncthreads();
+        T lm[LPC];
+        bool on[LPC];
+        double dot[LPC];
+#pragma unroll
+        for (int j = 0; j < LPC; ++j) {
+            const int c = c0 + lane + 64 * j;
+            dot[j] = 0.0;
+            lm[j] = (MODE == 1 && c < p) ? lam[c] : T(0);
+            on[j] = (MODE == 1 && c < p) ? active[c] != 0 : false;
+        }
+#pragma unroll
+        for (int i = 0; i < HALO_RPW; ++i) {
+            const int64_t row = r0 + wave + HALO_WAVES * i;
+            if (row >= r1) break;
+            T dv[LPC];
+            if (MODE == 1) {
+#pragma unroll
+                for (int j = 0; j < LPC; ++j) {
+                    const int c = c0 + lane + 64 * j;
+                    dv[j] = c < p ? X[row * p + c] : T(0);
+                }
+            }
+            T a1[LPC], a2[LPC];
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) { a1[j] = T(0); a2[j] = T(0); }
+            const int m = len[i];
+            int k = 0;
+            for (; k + 4 <= m; k += 4) {
+                T x[4][LPC], u1[4], u2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int o = __builtin_amdgcn_readlane(off[i], k + u);
+                    u1[u] = bcast(wa[i], k + u);
+                    u2[u] = bcast(wb[i], k + u);
+#pragma unroll
+                    for (int j = 0; j < LPC; ++j) x[u][j] = Xs[o + lane + 64 * j];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPC; ++j) {
+                        a1[j] = fma(u1[u], x[u][j], a1[j]);
+                        a2[j] = fma(u2[u], x[u][j], a2[j]);
+                    }
+            }
+            for (; k < m; ++k) {
+                const int o = __builtin_amdgcn_readlane(off[i], k);
+                const T u1 = bcast(wa[i], k), u2 = bcast(wb[i], k);
+#pragma unroll
+                for (int j = 0; j < LPC; ++j) {
+                    const T x = Xs[o + lane + 64 * j];
+                    a1[j] = fma(u1, x, a1[j]);
+                    a2[j] = fma(u2, x, a2[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) {
+                const int c = c0 + lane + 64 * j;
+                if (c >= p) continue;
+                if (MODE == 0) {
+                    if (Y2) {
+                        Y1[row * p + c] = a1[j];
+                        Y2[row * p + c] = a2[j];
+                    } else {
+                        Y1[row * p + c] = sel ? a2[j] : a1[j];
+                    }
+                } else {
+                    const T q = on[j] ? fma(-lm[j], a2[j], a1[j]) : T(0);
+                    dot[j] += (double)dv[j] * (double)q;
+                    Y1[row * p + c] = q;
+                }
+            }
+        }
+        __syncthreads();   // the slice is consumed
+        if (MODE == 1) {
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) red[wave * CP + lane + 64 * j] = dot[j];
+            __syncthreads();
+            for (int cl = threadIdx.x; cl < CP; cl += blockDim.x) {
+                const int c = c0 + cl;
+                if (c >= p) continue;
+                double sum = 0.0;
+#pragma unroll
+                for (int k2 = 0; k2 < HALO_WAVES; ++k2) sum += red[k2 * CP + cl];
+                part[b * p + c] = sum;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// out[g][c] = sum of rows [g G, (g + 1) G) of an nb x p partial matrix, in row
+// order; threads run over columns, so every read is coalesced.
+__global__ __launch_bounds__(256) void k_part_rows(int64_t nb, int p, int G, const double *__restrict__ in,
+                                                  double *__restrict__ out) {
+    const int64_t g = blockIdx.x;
+    const int64_t b0 = g * G, b1 = min(nb, b0 + G);
+    for (int c = threadIdx.x; c < p; c += blockDim.x) {
+        double sum = 0.0;
+        for (int64_t b = b0; b < b1; ++b) sum += in[b * p + c];
+        out[g * p + c] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -572,6 +807,54 @@ hipError_t launch_spmv_dot(hipStream_t s, int grid, int64_t n, const int64_t *rp
     hipLaunchKernelGGL(k_spmv_dot, dim3(grid), dim3(256), 0, s, n, rp, col, a, d, q, part);
     return hipGetLastError();
 }
+
+// Halo-SpMM launch: nb blocks of the plan (grid padded to whole XCD slabs).
+// MODE 1 also reduces the per-block dots: block partials go after the
+// ceil(nbp / HALO_G) group sums in part, the group sums to its start; the
+// caller's column sum takes *rows_out rows.  part_capacity in doubles.
+constexpr int HALO_G = 64;
+static int64_t halo_grid(int64_t nb) { return (nb + 7) / 8 * 8; }
+
+size_t spmm_halo_part_doubles(int64_t nb, int p) {
+    const int64_t nbp = halo_grid(nb);
+    return (size_t)((nbp + HALO_G - 1) / HALO_G + nbp) * p;
+}
+
+template <typename T>
+hipError_t launch_spmm_halo(hipStream_t s, int mode, int64_t nb, int p, const int64_t *row0, const int64_t *hoff,
+                            const int32_t *halo, const int64_t *rp, const uint16_t *lcol, const void *wv,
+                            const T *X, T *Y1, T *Y2, int sel, const T *lam, const uint8_t *active, double *part,
+                            size_t part_capacity, int *rows_out) {
+    using P2 = typename pair_t<T>::type;
+    const P2 *w = (const P2 *)wv;
+    const int64_t nbp = halo_grid(nb);
+    if (nbp <= 0 || nbp > 0x7fffffff) return hipErrorInvalidValue;
+    if (mode == 0) {
+        hipLaunchKernelGGL((k_spmm_halo<T, 0>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff,
+                           halo, rp, lcol, w, X, Y1, Y2, sel, lam, active, part);
+        return hipGetLastError();
+    }
+    const int64_t ng = (nbp + HALO_G - 1) / HALO_G;
+    if ((size_t)(ng + nbp) * p > part_capacity) return hipErrorInvalidValue;
+    double *bpart = part + ng * p;
+    hipLaunchKernelGGL((k_spmm_halo<T, 1>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff, halo,
+                       rp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
+    hipLaunchKernelGGL(k_part_rows, dim3((unsigned)ng), dim3(256), 0, s, nbp, p, HALO_G, bpart, part);
+    *rows_out = (int)ng;
+    return hipGetLastError();
+}
+
+template hipError_t launch_spmm_halo<double>(hipStream_t, int, int64_t, int, const int64_t *, const int64_t *,
+                                             const int32_t *, const int64_t *, const uint16_t *, const void *,
+                                             const double *, double *, double *, int, const double *,
+                                             const uint8_t *, double *, size_t, int *);
+template hipError_t launch_spmm_halo<float>(hipStream_t, int, int64_t, int, const int64_t *, const int64_t *,
+                                            const int32_t *, const int64_t *, const uint16_t *, const void *,
+                                            const float *, float *, float *, int, const float *, const uint8_t *,
+                                            double *, size_t, int *);
+int halo_max_rows() { return HALO_MAX; }
+int halo_max_block_rows() { return HALO_RMAX; }
+int halo_max_row_entries() { return HALO_EMAX; }
 
 template hipError_t launch_spmm_pair<double>(hipStream_t, int64_t, int, const int64_t *, const int32_t *,
                                              const void *, const double *, double *, double *, int);

@@ -30,6 +30,7 @@
 #include "../../include/ofks.h"
 #include "common.hpp"
 #include "dense.hpp"
+#include "halo_plan.hpp"
 
 namespace ofks {
 // launchers (k_spmm.hip)
@@ -41,6 +42,14 @@ hipError_t launch_spmm_shift(hipStream_t, int, int64_t, int, const int64_t *, co
                              const T *, const uint8_t *, const T *, T *, double *, int *);
 hipError_t launch_spmv_dot(hipStream_t, int, int64_t, const int64_t *, const int32_t *, const double *,
                            const double *, double *, double *);
+template <typename T>
+hipError_t launch_spmm_halo(hipStream_t, int, int64_t, int, const int64_t *, const int64_t *, const int32_t *,
+                            const int64_t *, const uint16_t *, const void *, const T *, T *, T *, int, const T *,
+                            const uint8_t *, double *, size_t, int *);
+size_t spmm_halo_part_doubles(int64_t nb, int p);
+int halo_max_rows();
+int halo_max_block_rows();
+int halo_max_row_entries();
 // (k_blas.hip)
 struct GradArgs {
     const void *HX;
@@ -190,6 +199,12 @@ struct ofks_ctx {
            *Ldiag = nullptr;
     double2 *hb = nullptr, *lb = nullptr;
     float2 *hb32 = nullptr, *lb32 = nullptr;
+    // LDS-halo SpMM plan: blocks of consecutive rows, their sorted distinct
+    // columns (halo) and each entry's slot in its block's halo
+    int64_t halo_nb = 0;                  // 0: no plan (a row alone exceeds the halo capacity)
+    int64_t *halo_row0 = nullptr, *halo_off = nullptr;
+    int32_t *halo_idx = nullptr;
+    uint16_t *halo_lcol = nullptr;
 
     // SCF work
     double *rho_q = nullptr, *eps_q = nullptr, *vxc_q = nullptr, *veff_q = nullptr, *bvec = nullptr,
@@ -490,7 +505,49 @@ size_t partials_needed(ofks_ctx *c, int p) {
     need = std::max(need, (size_t)c->gemm_rows * gy * (1 + p));
     need = std::max(need, (size_t)c->grid * std::max(p, 5));
     need = std::max(need, (size_t)3 * 1024);
+    if (c->halo_nb) need = std::max(need, spmm_halo_part_doubles(c->halo_nb, p));   // either precision
     return need;
+}
+
+// SpMM kernel choice: the LDS-halo kernel for wide FP64 blocks (measured
+// faster there), the row-gather kernel otherwise (spmm_mode 0); forced by
+// spmm_mode 1 (gather) or 2 (halo).  1: halo, 0: gather, -1: halo forced but
+// no plan exists.
+int halo_choice(ofks_ctx *c, int p, size_t elem) {
+    const int m = c->prm.spmm_mode;
+    if (m == 1) return 0;
+    if (m == 2) return c->halo_nb ? 1 : -1;
+    return c->halo_nb && p >= 64 && elem == 8 ? 1 : 0;
+}
+
+// Y1 = A1 X, Y2 = A2 X (Y2 = NULL: A1 X or A2 X by sel) for the pair matrix w.
+template <typename T>
+int spmm_pair(ofks_ctx *c, int p, const void *w, const T *X, T *Y1, T *Y2, int sel) {
+    const int h = halo_choice(c, p, sizeof(T));
+    if (h < 0) return fail(c, OFKS_ESTATE, "spmm_mode halo: no halo plan for this matrix");
+    if (h)
+        HIPCHK(launch_spmm_halo<T>(c->stream, 0, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->rp,
+                                   c->halo_lcol, w, X, Y1, Y2, sel, nullptr, nullptr, nullptr, 0, nullptr));
+    else
+        HIPCHK(launch_spmm_pair<T>(c->stream, c->n, p, c->rp, c->col, w, X, Y1, Y2, sel));
+    return OFKS_OK;
+}
+
+// Q = (L/2 - lam B) D on active columns and per-block <D, Q> partials in
+// c->part; *used = partial rows for the column sum.
+template <typename T>
+int spmm_shift(ofks_ctx *c, int p, const void *lb, const T *lam, const uint8_t *act, const T *D, T *Q, int *used) {
+    const int h = halo_choice(c, p, sizeof(T));
+    if (h < 0) return fail(c, OFKS_ESTATE, "spmm_mode halo: no halo plan for this matrix");
+    if (h) {
+        CHK(ensure_part(c, spmm_halo_part_doubles(c->halo_nb, p)));
+        HIPCHK(launch_spmm_halo<T>(c->stream, 1, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->rp,
+                                   c->halo_lcol, lb, D, Q, nullptr, 0, lam, act, c->part, c->part_cap, used));
+        return OFKS_OK;
+    }
+    CHK(ensure_part(c, (size_t)c->grid * p));
+    HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, c->n, p, c->rp, c->col, lb, lam, act, D, Q, c->part, used));
+    return OFKS_OK;
 }
 
 // column sums of A .* B over rows (FP64)
@@ -641,7 +698,7 @@ int pcg_run(ofks_ctx *c, int m, int64_t n, int p, const uint8_t *act, const T *l
         int used = 0;
         {
             Scope sc(c, "spmm_shift");
-            HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, n, p, c->rp, c->col, lb, lam, act, D, Q, c->part, &used));
+            CHK(spmm_shift<T>(c, p, lb, lam, act, D, Q, &used));
         }
         HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
         HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, rz, alpha));
@@ -674,7 +731,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         if (c->k > 0 && !plam) {
             {
                 Scope sc(c, "spmm_dual");
-                HIPCHK(launch_spmm_pair<T>(c->stream, n, p, c->rp, c->col, hbT<T>(c), B.Xt, B.BX, nullptr, 1));
+                CHK(spmm_pair<T>(c, p, hbT<T>(c), B.Xt, B.BX, nullptr, 1));
             }
             std::vector<double> d2;
             CHK(coldot<T>(c, B.Xt, B.BX, d2));
@@ -691,7 +748,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     // HX~, BX~
     {
         Scope sc(c, "spmm_dual");
-        HIPCHK(launch_spmm_pair<T>(c->stream, n, p, c->rp, c->col, hbT<T>(c), B.Xt, B.HX, B.BX, 0));
+        CHK(spmm_pair<T>(c, p, hbT<T>(c), B.Xt, B.HX, B.BX, 0));
     }
     std::vector<double> St, Lt;
     CHK(gram<T>(c, B.Xt, B.BX, B.HX, St, Lt));
@@ -867,10 +924,8 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
                 c->lp_u = u;
                 c->lp_u_bytes = bytes;
             }
-            CHK(ensure_part(c, (size_t)c->grid * p));
             int used = 0;
-            HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, n, p, c->rp, c->col, lbT<T>(c), B.lam, c->active, B.D,
-                                        (T *)c->lp_u, c->part, &used));
+            CHK(spmm_shift<T>(c, p, lbT<T>(c), B.lam, c->active, B.D, (T *)c->lp_u, &used));
         }
     }
 
@@ -977,6 +1032,52 @@ int ensure_f32_matrices(ofks_ctx *c) {
     return OFKS_OK;
 }
 
+void free_halo(ofks_ctx *c) {
+    dfree(c, c->halo_row0);
+    dfree(c, c->halo_off);
+    dfree(c, c->halo_idx);
+    dfree(c, c->halo_lcol);
+    c->halo_nb = 0;
+}
+
+// LDS-halo plan from the CSR pattern on the device (halo_plan.hpp), checked
+// independently on the host before upload.  A row with more entries than a
+// wave has lanes, or alone more columns than the halo holds, leaves no plan:
+// the row-gather kernel serves every p then.
+int build_halo_plan(ofks_ctx *c) {
+    free_halo(c);
+    const int64_t n = c->n, nnz = c->nnz;
+    std::vector<int64_t> rp(n + 1);
+    std::vector<int32_t> col(nnz);
+    HIPCHK(hipMemcpyAsync(rp.data(), c->rp, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(col.data(), c->col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (rp[n] != nnz) return fail(c, OFKS_EINVAL, "csr: row_ptr[n] != nnz");
+    const int HM = halo_max_rows(), RM = halo_max_block_rows(), EM = halo_max_row_entries();
+    HaloPlan P;
+    int64_t where = 0;
+    int rc = halo_plan_build(n, rp.data(), col.data(), HM, RM, EM, P, &where);
+    if (rc == HALO_TOO_WIDE) return OFKS_OK;
+    if (rc == HALO_BAD_ROWPTR) return fail(c, OFKS_EINVAL, "csr: row_ptr malformed at row %lld", (long long)where);
+    if (rc == HALO_BAD_COLUMN) return fail(c, OFKS_EINVAL, "csr: column index out of range at entry %lld",
+                                           (long long)where);
+    if (rc != HALO_OK || halo_plan_check(n, rp.data(), col.data(), HM, RM, EM, P, &where) != HALO_OK)
+        return fail(c, OFKS_EINTERNAL, "halo plan: consistency check failed at %lld", (long long)where);
+    const int64_t nb = P.nb();
+    CHK(dalloc(c, &c->halo_row0, nb + 1));
+    CHK(dalloc(c, &c->halo_off, nb + 1));
+    CHK(dalloc(c, &c->halo_idx, P.halo.size()));
+    CHK(dalloc(c, &c->halo_lcol, nnz));
+    HIPCHK(hipMemcpyAsync(c->halo_row0, P.row0.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->halo_off, P.hoff.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->halo_idx, P.halo.data(), P.halo.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(c->halo_lcol, P.lcol.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->halo_nb = nb;
+    return OFKS_OK;
+}
+
 int alloc_system_common(ofks_ctx *c) {
     CHK(dalloc(c, &c->lhd, c->n));
     CHK(dalloc(c, &c->bd, c->n));
@@ -1001,6 +1102,7 @@ void free_system(ofks_ctx *c) {
     dfree(c, c->hd);
     dfree(c, c->Ldiag);
     dfree(c, c->red);
+    free_halo(c);
     c->has_system = false;
     c->assembled = false;
     c->has_lhalf = false;
@@ -1235,6 +1337,7 @@ int ofks_assemble(ofks_ctx *c) {
     CHK(dalloc(c, &c->cg_sc, 8));
     CHK(dalloc(c, &c->cg_part, 4 * CG_BLOCKS));
     HIPCHK(hipMemsetAsync(c->U, 0, n * sizeof(double), s));
+    CHK(build_halo_plan(c));
     c->has_system = true;
     c->assembled = true;
     c->has_lhalf = true;
@@ -1310,6 +1413,7 @@ int ofks_csr_load(ofks_ctx *c, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     HIPCHK(hipStreamSynchronize(s));
     dfree(c, errd);
     if (errh) return fail(c, OFKS_EINVAL, "csr_load: a row has no diagonal entry");
+    CHK(build_halo_plan(c));
     c->has_system = true;
     c->assembled = false;
     c->has_x = false;
@@ -1321,7 +1425,8 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
     if (!(prm->beta >= 0.0) || !(prm->tol > 0.0) || prm->max_iter < 0 || prm->pcg_iters < 0 ||
         prm->precond < 0 || prm->precond > 2 || prm->step_rule < 0 || prm->step_rule > 4 ||
         (prm->precision != OFKS_F64 && prm->precision != OFKS_F32) || prm->fallback_rule < 0 ||
-        prm->fallback_rule > 1 || prm->algorithm < 0 || prm->algorithm > 1)
+        prm->fallback_rule > 1 || prm->algorithm < 0 || prm->algorithm > 1 || prm->spmm_mode < 0 ||
+        prm->spmm_mode > 2)
         return fail(c, OFKS_EINVAL, "set_params: invalid parameter");
     if (prm->precond == OFKS_PRECOND_PAPER && prm->pcg_iters < 1)
         return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs pcg_iters >= 1");
@@ -1360,7 +1465,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     HIPCHK(hipMemcpyAsync(B.Xt, X0, (size_t)c->n * p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (orth) {
         // Cholesky-based Gram-Schmidt: V^T B V = R^T R, X0 = V R^-1
-        HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, B.Xt, B.BX, nullptr, 1));
+        CHK(spmm_pair<double>(c, p, c->hb, B.Xt, B.BX, nullptr, 1));
         std::vector<double> St, Lt;
         CHK(gram<double>(c, B.Xt, B.BX, B.BX, St, Lt));
         for (int a = 0; a < p; ++a)
@@ -1379,7 +1484,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
         std::swap(B.Xt, B.HX);
     } else {
         // a block taken as given must have no column of zero B-norm
-        HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, B.Xt, B.BX, nullptr, 1));
+        CHK(spmm_pair<double>(c, p, c->hb, B.Xt, B.BX, nullptr, 1));
         std::vector<double> bn;
         CHK(coldot<double>(c, B.Xt, B.BX, bn));
         for (int i = 0; i < p; ++i)
@@ -1519,7 +1624,7 @@ int ofks_postprocess(ofks_ctx *c, double *eigs) {
     c->dinv_h = ones;
     CHK(upload<double>(c, B.dinv, ones));
     if (c->prm.scf) CHK(build_h<double>(c, B.Xt, B.dinv));
-    HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, B.Xt, B.HX, B.BX, 0));
+    CHK(spmm_pair<double>(c, p, c->hb, B.Xt, B.HX, B.BX, 0));
     std::vector<double> St, Lt;
     CHK(gram<double>(c, B.Xt, B.BX, B.HX, St, Lt));
     std::vector<double> S(p * p), L0(p * p);
@@ -1557,7 +1662,7 @@ int ofks_spmm(ofks_ctx *c, int32_t p, const double *X, double *HX, double *BX) {
     if (!c) return OFKS_EINVAL;
     if (!c->has_system) return fail(c, OFKS_ESTATE, "spmm: no system");
     if (p <= 0 || p > 1024 || !X || !HX || !BX) return fail(c, OFKS_EINVAL, "spmm: bad arguments");
-    HIPCHK(launch_spmm_pair<double>(c->stream, c->n, p, c->rp, c->col, c->hb, X, HX, BX, 0));
+    CHK(spmm_pair<double>(c, p, c->hb, X, HX, BX, 0));
     return sync(c);
 }
 

@@ -159,6 +159,8 @@ class Solver:
                 v = _lib.PRECISION[v]
             elif k == "algorithm" and isinstance(v, str):
                 v = {"pcal": 0, "plam": 1}[v]
+            elif k == "spmm_mode" and isinstance(v, str):
+                v = {"auto": 0, "gather": 1, "halo": 2}[v]
             elif k == "fallback_rule" and isinstance(v, str):
                 v = {"min": 0, "max": 1}[v]
             elif k == "precond_lambda" and isinstance(v, str):

@@ -46,10 +46,12 @@ def test_full_size_csr_is_bit_exact(c3):
     assert _relerr(g["H"], d.H) < 1e-12
 
 
-def test_full_size_products_and_gram(c3):
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+def test_full_size_products_and_gram(mode, c3):
     import torch
     w, d, s = c3
-    print("[gpu] full size SpMM and Gram p=128", flush=True)
+    print(f"[gpu] full size SpMM ({mode}) and Gram p=128", flush=True)
+    s.set_params(spmm_mode=mode)
     X = wl.random_block(77, d.n, w.p)
     Xd = _dev(X)
     HXd, BXd = s.spmm(Xd)
@@ -67,16 +69,17 @@ def test_full_size_products_and_gram(c3):
     assert _relerr(L0, X.T @ HX) < 1e-12
 
 
-def test_full_size_preconditioner(c3):
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+def test_full_size_preconditioner(mode, c3):
     import torch
     w, d, s = c3
-    print("[gpu] full size preconditioner p=128 m=10", flush=True)
+    print(f"[gpu] full size preconditioner ({mode}) p=128 m=10", flush=True)
     prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
     rng = np.random.default_rng(9)
     G = rng.standard_normal((d.n, w.p))
     lam = -np.abs(rng.standard_normal(w.p)) * 3.0 - 0.05
     lam[7] = 0.2                                   # identity branch
-    s.set_params(precond="paper", pcg_iters=10)
+    s.set_params(precond="paper", pcg_iters=10, spmm_mode=mode)
     P = s.precondition(lam, _dev(G))
     ref = pcal.precondition(prob, G, lam, pcal.Params(precond="paper", pcg_iters=10))
     rows = np.sort(rng.choice(d.n, 5000, replace=False))

@@ -72,11 +72,15 @@ def test_csr_pattern_bit_exact_and_values(which, c1, graded):
     assert _relerr(g["H"], d.H) < 1e-13
 
 
+@pytest.mark.parametrize("mode", ["gather", "halo"])
 @pytest.mark.parametrize("p", [1, 3, 4, 11, 16, 33, 64, 128, 130, 260, 512])
-def test_dual_spmm(p, graded):
+def test_dual_spmm(p, mode, graded):
+    """Both SpMM kernels: row-gather, and LDS-halo (p = 33, 130, 260: a ragged
+    last 512-byte column slice)."""
     w, d = graded
-    print(f"[gpu] spmm p={p}", flush=True)
+    print(f"[gpu] spmm p={p} mode={mode}", flush=True)
     s = _solver_for(w)
+    s.set_params(spmm_mode=mode)
     X = np.random.default_rng(p).standard_normal((d.n, p))
     HX, BX = s.spmm(_dev(X))
     assert _relerr(_host(HX), native.spmm(d.row_ptr, d.col, d.H, X)) < 1e-12
@@ -95,12 +99,13 @@ def test_gram(p, graded):
     assert _relerr(L0, X.T @ HX) < 1e-12
 
 
+@pytest.mark.parametrize("mode", ["gather", "halo"])
 @pytest.mark.parametrize("p", [1, 5, 16, 128, 130, 512])
-def test_preconditioner_cg(p, graded):
+def test_preconditioner_cg(p, mode, graded):
     w, d = graded
-    print(f"[gpu] precondition p={p}", flush=True)
+    print(f"[gpu] precondition p={p} mode={mode}", flush=True)
     s = _solver_for(w)
-    s.set_params(precond="paper", pcg_iters=10)
+    s.set_params(precond="paper", pcg_iters=10, spmm_mode=mode)
     prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
     rng = np.random.default_rng(7 + p)
     G = rng.standard_normal((d.n, p))
@@ -110,6 +115,53 @@ def test_preconditioner_cg(p, graded):
     P = _host(s.precondition(lam, _dev(G)))
     ref = pcal.precondition(prob, G, lam, pcal.Params(precond="paper", pcg_iters=10))
     assert _relerr(P, ref) < 1e-11
+
+
+def test_matrix_without_halo_plan_uses_row_gather():
+    """csr_load of a pattern with a row wider than the LDS halo: no halo plan,
+    the automatic choice takes the row-gather kernel, a forced halo kernel is
+    an error."""
+    import scipy.sparse as sp
+    from paper_2007_14228_amd import Solver
+    print("[gpu] csr_load wide row", flush=True)
+    n, p = 300, 64
+    rng = np.random.default_rng(4)
+    A = sp.diags([np.ones(n - 1), 4.0 * np.ones(n), np.ones(n - 1)], [-1, 0, 1], format="lil")
+    A[1, :250] = rng.standard_normal(250)
+    A[1, 1] = 5.0
+    A = A.tocsr()
+    A.sort_indices()
+    rp, col = A.indptr.astype(np.int64), A.indices.astype(np.int32)
+    H, B = A.data.copy(), np.abs(A.data) + 1.0
+    s = Solver()
+    s.csr_load(_dev(rp), _dev(col), _dev(H), _dev(B), _dev(0.5 * H))
+    X = rng.standard_normal((n, p))
+    HX, BX = s.spmm(_dev(X))
+    Bm = sp.csr_matrix((B, col, rp), shape=(n, n))
+    assert _relerr(_host(HX), A @ X) < 1e-12
+    assert _relerr(_host(BX), Bm @ X) < 1e-12
+    s.set_params(spmm_mode="halo")
+    with pytest.raises(RuntimeError):
+        s.spmm(_dev(X))
+
+
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+def test_step_parity_in_both_spmm_modes(mode, c1):
+    """Three FP64 iterations with the paper preconditioner at p = 72 (two
+    column slices, the second ragged) through each SpMM kernel."""
+    w, d = c1
+    p = 72
+    print(f"[gpu] step parity c1 p={p} mode={mode}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(8, d.n, p))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=3, precond="paper"))
+    s = _solver_for(w)
+    st = _run_gpu(s, X0, 3, beta=w.beta, tol=1e-30, precond="paper", pcg_iters=10, energy_every=1,
+                  spmm_mode=mode)
+    assert len(st) == len(hist) == 4
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-10 * b.kkt
+        assert abs(a["energy"] - b.energy) <= 1e-11 * abs(b.energy)
 
 
 def _run_gpu(s, X0, max_iter, **params):
