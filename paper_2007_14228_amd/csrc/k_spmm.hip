@@ -460,16 +460,16 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 // block, and the waves per SIMD the register budget is cut for (set by how
 // many blocks the LDS admits per CU).
 #ifndef OFKS_HALO_MAX
-#define OFKS_HALO_MAX 160
+#define OFKS_HALO_MAX 80
 #endif
 #ifndef OFKS_HALO_RMAX
-#define OFKS_HALO_RMAX 64
+#define OFKS_HALO_RMAX 32
 #endif
 #ifndef OFKS_HALO_WAVES
 #define OFKS_HALO_WAVES 8
 #endif
 #ifndef OFKS_HALO_WPE
-#define OFKS_HALO_WPE 4
+#define OFKS_HALO_WPE 6
 #endif
 constexpr int HALO_MAX = OFKS_HALO_MAX, HALO_RMAX = OFKS_HALO_RMAX, HALO_WAVES = OFKS_HALO_WAVES, HALO_EMAX = 64;
 constexpr int HALO_RPW = HALO_RMAX / HALO_WAVES;   // rows per wave
