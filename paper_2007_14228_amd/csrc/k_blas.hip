@@ -368,11 +368,14 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int p, int64_t row
         }
 }
 
+#ifndef OFKS_RG_KC
+#define OFKS_RG_KC 16   // K values staged per LDS round
+#endif
 template <typename T, int NTW, int EPI>
 __global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A,
                                                      const T *__restrict__ sa, const T *__restrict__ M,
                                                      T *__restrict__ Y, GradArgs ga) {
-    constexpr int TR = 64, TC = 16 * NTW, KC = 16;
+    constexpr int TR = 64, TC = 16 * NTW, KC = OFKS_RG_KC;
     using acc_t = typename mfma4<T>::type;
     __shared__ T As[TR][KC + 1];
     __shared__ T Ms[KC][TC];

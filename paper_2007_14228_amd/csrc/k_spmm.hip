@@ -809,9 +809,9 @@ hipError_t launch_spmv_dot(hipStream_t s, int grid, int64_t n, const int64_t *rp
 }
 
 // Halo-SpMM launch: nb blocks of the plan (grid padded to whole XCD slabs).
-// MODE 1 also reduces the per-block dots: block partials go after the
-// ceil(nbp / HALO_G) group sums in part, the group sums to its start; the
-// caller's column sum takes *rows_out rows.  part_capacity in doubles.
+// MODE 1 leaves the per-block dots after room for ceil(nbp / HALO_G) group
+// sums in part; launch_halo_part_rows then writes the group sums to its start
+// and the caller's column sum takes *rows_out rows.  part_capacity in doubles.
 constexpr int HALO_G = 64;
 static int64_t halo_grid(int64_t nb) { return (nb + 7) / 8 * 8; }
 
@@ -839,8 +839,14 @@ hipError_t launch_spmm_halo(hipStream_t s, int mode, int64_t nb, int p, const in
     double *bpart = part + ng * p;
     hipLaunchKernelGGL((k_spmm_halo<T, 1>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff, halo,
                        rp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
-    hipLaunchKernelGGL(k_part_rows, dim3((unsigned)ng), dim3(256), 0, s, nbp, p, HALO_G, bpart, part);
     *rows_out = (int)ng;
+    return hipGetLastError();
+}
+
+// The group sums of a MODE 1 halo launch's per-block dots (fixed order).
+hipError_t launch_halo_part_rows(hipStream_t s, int64_t nb, int p, double *part) {
+    const int64_t nbp = halo_grid(nb), ng = (nbp + HALO_G - 1) / HALO_G;
+    hipLaunchKernelGGL(k_part_rows, dim3((unsigned)ng), dim3(256), 0, s, nbp, p, HALO_G, part + ng * p, part);
     return hipGetLastError();
 }
 

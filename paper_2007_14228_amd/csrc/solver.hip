@@ -47,6 +47,7 @@ hipError_t launch_spmm_halo(hipStream_t, int, int64_t, int, const int64_t *, con
                             const int64_t *, const uint16_t *, const void *, const T *, T *, T *, int, const T *,
                             const uint8_t *, double *, size_t, int *);
 size_t spmm_halo_part_doubles(int64_t nb, int p);
+hipError_t launch_halo_part_rows(hipStream_t, int64_t, int, double *);
 int halo_max_rows();
 int halo_max_block_rows();
 int halo_max_row_entries();
@@ -534,18 +535,24 @@ int spmm_pair(ofks_ctx *c, int p, const void *w, const T *X, T *Y1, T *Y2, int s
 }
 
 // Q = (L/2 - lam B) D on active columns and per-block <D, Q> partials in
-// c->part; *used = partial rows for the column sum.
+// c->part; *used = partial rows for the column sum.  The product kernel is
+// timed as "spmm_shift", the halo kernel's partial-row sums apart from it.
 template <typename T>
 int spmm_shift(ofks_ctx *c, int p, const void *lb, const T *lam, const uint8_t *act, const T *D, T *Q, int *used) {
     const int h = halo_choice(c, p, sizeof(T));
     if (h < 0) return fail(c, OFKS_ESTATE, "spmm_mode halo: no halo plan for this matrix");
     if (h) {
         CHK(ensure_part(c, spmm_halo_part_doubles(c->halo_nb, p)));
-        HIPCHK(launch_spmm_halo<T>(c->stream, 1, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->rp,
-                                   c->halo_lcol, lb, D, Q, nullptr, 0, lam, act, c->part, c->part_cap, used));
+        {
+            Scope sc(c, "spmm_shift");
+            HIPCHK(launch_spmm_halo<T>(c->stream, 1, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->rp,
+                                       c->halo_lcol, lb, D, Q, nullptr, 0, lam, act, c->part, c->part_cap, used));
+        }
+        HIPCHK(launch_halo_part_rows(c->stream, c->halo_nb, p, c->part));
         return OFKS_OK;
     }
     CHK(ensure_part(c, (size_t)c->grid * p));
+    Scope sc(c, "spmm_shift");
     HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, c->n, p, c->rp, c->col, lb, lam, act, D, Q, c->part, used));
     return OFKS_OK;
 }
@@ -696,10 +703,7 @@ int pcg_run(ofks_ctx *c, int m, int64_t n, int p, const uint8_t *act, const T *l
     CHK(ensure_part(c, (size_t)c->grid * p));
     for (int it = 0; it < m; ++it) {
         int used = 0;
-        {
-            Scope sc(c, "spmm_shift");
-            CHK(spmm_shift<T>(c, p, lb, lam, act, D, Q, &used));
-        }
+        CHK(spmm_shift<T>(c, p, lb, lam, act, D, Q, &used));
         HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
         HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, rz, alpha));
         const bool more = it + 1 < m;   // the last iteration needs no new residual or direction
