@@ -380,28 +380,75 @@ __global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, c
     __shared__ T As[TR][KC + 1];
     __shared__ T Ms[KC][TC];
     __shared__ double red[256];
+    // per-column epilogue constants of this block's column tile, fixed for the
+    // launch (in LDS rather than registers: it keeps more waves resident)
+    __shared__ T scl_s[TC], lmc_s[TC];
+    __shared__ uint8_t act_s[TC];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int c0 = blockIdx.y * TC;
     const int64_t ntiles = (n + TR - 1) / TR;
     double r2 = 0.0;
     double rz[NTW];
-    // this lane's output columns are fixed for the whole launch
-    T scl[NTW], lmc[NTW];
-    bool act[NTW];
 #pragma unroll
-    for (int t = 0; t < NTW; ++t) {
-        rz[t] = 0.0;
-        const int c = c0 + 16 * t + li;
+    for (int t = 0; t < NTW; ++t) rz[t] = 0.0;
+    for (int cl = threadIdx.x; cl < TC; cl += 256) {
+        const int c = c0 + cl;
         const int cc = c < p ? c : c - p;
-        scl[t] = (EPI != EPI_PLAIN && c < N) ? sa[cc] : T(0);
-        lmc[t] = (EPI == EPI_GRAD_PCG && c < p) ? ((const T *)ga.lam)[c] : T(0);
-        act[t] = (EPI == EPI_GRAD_PCG && c < p) ? ga.active[c] != 0 : false;
+        scl_s[cl] = (EPI != EPI_PLAIN && c < N) ? sa[cc] : T(0);
+        lmc_s[cl] = (EPI == EPI_GRAD_PCG && c < p) ? ((const T *)ga.lam)[c] : T(0);
+        act_s[cl] = (EPI == EPI_GRAD_PCG && c < p) ? ga.active[c] : 0;
     }
+    __syncthreads();
     const T *__restrict__ HX = (const T *)ga.HX;
     T *__restrict__ Pout = (T *)ga.P;
     T *__restrict__ Rout = (T *)ga.R;
     T *__restrict__ Dout = (T *)ga.D;
+
+    // K-chunk staging, software-pipelined: the values of the next chunk (of
+    // this tile, or the next tile's first) are loaded into registers before
+    // the current chunk's MFMAs and stored to LDS after them
+    // Thread t moves AR consecutive k of one A row and MR consecutive columns
+    // of one M row per chunk (16-byte loads when the chunk is whole and the
+    // rows are 16-byte aligned; element loads with bounds otherwise).
+    constexpr int AR = TR * KC / 256, MR = KC * TC / 256;
+    static_assert(AR * 256 == TR * KC && MR * 256 == KC * TC && KC % AR == 0 && TC % MR == 0, "chunk split");
+    constexpr int VWT = 16 / sizeof(T);
+    static_assert(AR % VWT == 0 && MR % VWT == 0, "16-byte pieces");
+    const int a_rr = threadIdx.x * AR / KC, a_kk = threadIdx.x * AR % KC;
+    const int m_kk = threadIdx.x * MR / TC, m_cc = threadIdx.x * MR % TC;
+    const bool avec = p % VWT == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
+    const bool mvec = N % VWT == 0 && reinterpret_cast<uintptr_t>(M) % 16 == 0 && c0 + TC <= N;
+    T ar[AR], mr[MR];
+    auto load_chunk = [&](int64_t tile, int k0) {
+        const int64_t r = tile * TR + a_rr;
+        const bool kin = k0 + KC <= p;
+        if (avec && kin && r < n) {
+#pragma unroll
+            for (int q = 0; q < AR; q += VWT) load_vec<T, VWT>(A + r * p + k0 + a_kk + q, *reinterpret_cast<T(*)[VWT]>(&ar[q]));
+        } else {
+#pragma unroll
+            for (int j = 0; j < AR; ++j) ar[j] = (r < n && k0 + a_kk + j < p) ? A[r * p + k0 + a_kk + j] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < AR; ++j) ar[j] = k0 + a_kk + j < p ? ar[j] * sa[k0 + a_kk + j] : T(0);
+        const int k = k0 + m_kk;
+        if (mvec && kin) {
+#pragma unroll
+            for (int q = 0; q < MR; q += VWT)
+                load_vec<T, VWT>(M + (int64_t)k * N + c0 + m_cc + q, *reinterpret_cast<T(*)[VWT]>(&mr[q]));
+        } else {
+#pragma unroll
+            for (int j = 0; j < MR; ++j) mr[j] = (k < p && c0 + m_cc + j < N) ? M[(int64_t)k * N + c0 + m_cc + j] : T(0);
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int j = 0; j < AR; ++j) As[a_rr][a_kk + j] = ar[j];
+#pragma unroll
+        for (int j = 0; j < MR; ++j) Ms[m_kk][m_cc + j] = mr[j];
+    };
+    if ((int64_t)blockIdx.x < ntiles) load_chunk(blockIdx.x, 0);
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * TR;
@@ -409,18 +456,11 @@ __global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, c
 #pragma unroll
         for (int t = 0; t < NTW; ++t) acc[t] = acc_t{T(0), T(0), T(0), T(0)};
         for (int k0 = 0; k0 < p; k0 += KC) {
-            for (int idx = threadIdx.x; idx < TR * KC; idx += 256) {
-                const int rr = idx / KC, kk = idx % KC;
-                const int64_t r = r0 + rr;
-                const int k = k0 + kk;
-                As[rr][kk] = (r < n && k < p) ? A[r * p + k] * sa[k] : T(0);
-            }
-            for (int idx = threadIdx.x; idx < KC * TC; idx += 256) {
-                const int kk = idx / TC, cc = idx % TC;
-                const int k = k0 + kk, c = c0 + cc;
-                Ms[kk][cc] = (k < p && c < N) ? M[(int64_t)k * N + c] : T(0);
-            }
+            store_chunk();
             __syncthreads();
+            const bool last = k0 + KC >= p;
+            const int64_t nt = last ? tile + gridDim.x : tile;
+            if (nt < ntiles) load_chunk(nt, last ? 0 : k0 + KC);
 #pragma unroll
             for (int s4 = 0; s4 < KC / 4; ++s4) {
                 const T a = As[16 * w + li][4 * s4 + lk];
@@ -456,7 +496,7 @@ __global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, c
                     Y[r * N + c] = val;
                     continue;
                 }
-                const T v = fma(hx[t], scl[t], val);
+                const T v = fma(hx[t], scl_s[16 * t + li], val);
                 if (c >= p) {
                     r2 += (double)v * (double)v;
                 } else if (EPI == EPI_GRAD) {
@@ -465,8 +505,8 @@ __global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, c
                     Pout[r * p + c] = v;
                     rz[t] += (double)v * (double)v;
                 } else {  // EPI_GRAD_PCG
-                    if (act[t]) {
-                        const T z = v * (T(1) / (ld - lmc[t] * bdv));
+                    if (act_s[16 * t + li]) {
+                        const T z = v * (T(1) / (ld - lmc_s[16 * t + li] * bdv));
                         Rout[r * p + c] = v;
                         Dout[r * p + c] = z;
                         rz[t] += (double)v * (double)z;
