@@ -86,3 +86,14 @@ def test_c4_full_size():
     assert all(np.isfinite(x["kkt"]) and np.isfinite(x["fea"]) for x in st)
     assert st[0]["fea"] < 1e-3                      # B-orthonormal start, in FP32
     assert st[-1]["kkt"] < st[0]["kkt"]
+    # the same iteration continued through each SpMM kernel (FP32, four 512-byte slices per row), timed
+    for mode in ("gather", "halo"):
+        s.set_params(beta=w.beta, tol=1e-30, max_iter=100, precond="paper", pcg_iters=10, precision="f32",
+                     refine_tol=0.0, energy_every=10, spmm_mode=mode)
+        s.timing(True)
+        st2, _, _ = s.step(2)
+        ms, cnt = s.timer("spmm_shift")
+        md, cd = s.timer("spmm_dual")
+        print(f"[gpu] c4: spmm {mode}: shift {ms / max(cnt, 1):.3f} ms x {cnt}, dual {md / max(cd, 1):.3f} ms; "
+              f"kkt={st2[-1]['kkt']:.4e}", flush=True)
+        assert all(np.isfinite(x["kkt"]) for x in st2)
