@@ -488,7 +488,8 @@ __device__ __forceinline__ float bcast(float v, int k) {
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu(OFKS_HALO_WPE))) void k_spmm_halo(
     int64_t nb, int p, const int64_t *__restrict__ row0, const int64_t *__restrict__ hoff,
-    const int32_t *__restrict__ halo, const int64_t *__restrict__ rp, const uint16_t *__restrict__ lcol,
+    const int32_t *__restrict__ halo, const int32_t *__restrict__ rbase, const int64_t *__restrict__ rp,
+    const uint16_t *__restrict__ lcol,
     const typename pair_t<T>::type *__restrict__ w, const T *__restrict__ X, T *__restrict__ Y1,
     T *__restrict__ Y2, int sel, const T *__restrict__ lam, const uint8_t *__restrict__ active,
     double *__restrict__ part) {
@@ -498,6 +499,10 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
     constexpr int LPC = CP / 64;          // columns per lane in a slice
     constexpr int SEG = CP / VW;
     __shared__ T Xs[HALO_MAX * CP];
+    // per-wave broadcast area: the current row's entries, read back by every
+    // lane at a uniform address (an LDS broadcast instead of VALU readlanes)
+    __shared__ int ent_off[HALO_WAVES][64];
+    __shared__ P2 ent_w[HALO_WAVES][64];
     // MODE 1 per-wave dot partials reuse the slice's LDS once it is consumed
     static_assert(HALO_WAVES * CP * sizeof(double) <= sizeof(T) * HALO_MAX * CP, "partials fit in the slice");
     double *red = reinterpret_cast<double *>(Xs);
@@ -511,6 +516,7 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
     }
     const int64_t r0 = row0[b], r1 = row0[b + 1], h0 = hoff[b];
     const int hn = (int)(hoff[b + 1] - h0);
+    const int rb = MODE == 1 ? rbase[b] : 0;   // the block's rows sit at halo slots rb, rb + 1, ...
     // 16-byte loads need every row start 16-byte aligned
     const bool vec = p % VW == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
     // staging: thread t always moves 16-byte segment t % SEG of halo slots
@@ -585,45 +591,51 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
         for (int i = 0; i < HALO_RPW; ++i) {
             const int64_t row = r0 + wave + HALO_WAVES * i;
             if (row >= r1) break;
-            T dv[LPC];
+            T dv[LPC];   // D's own row, staged with the halo
             if (MODE == 1) {
 #pragma unroll
-                for (int j = 0; j < LPC; ++j) {
-                    const int c = c0 + lane + 64 * j;
-                    dv[j] = c < p ? X[row * p + c] : T(0);
-                }
+                for (int j = 0; j < LPC; ++j) dv[j] = Xs[(rb + (int)(row - r0)) * CP + lane + 64 * j];
             }
             T a1[LPC], a2[LPC];
 #pragma unroll
             for (int j = 0; j < LPC; ++j) { a1[j] = T(0); a2[j] = T(0); }
             const int m = len[i];
+            // the row's entries into this wave's broadcast area (LDS keeps a
+            // wave's accesses in order; the wave barriers keep the compiler's)
+            __builtin_amdgcn_wave_barrier();
+            ent_off[wave][lane] = off[i];
+            ent_w[wave][lane] = P2{wa[i], wb[i]};
+            __builtin_amdgcn_wave_barrier();
+            // entries in flight per step (the FP64 shifted product holds more
+            // state per lane, so it takes two to stay within its registers)
+            constexpr int UN = (MODE == 1 && sizeof(T) == 8) ? 2 : 4;
             int k = 0;
-            for (; k + 4 <= m; k += 4) {
-                T x[4][LPC], u1[4], u2[4];
+            for (; k + UN <= m; k += UN) {
+                T x[UN][LPC];
+                P2 ww[UN];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int o = __builtin_amdgcn_readlane(off[i], k + u);
-                    u1[u] = bcast(wa[i], k + u);
-                    u2[u] = bcast(wb[i], k + u);
+                for (int u = 0; u < UN; ++u) {
+                    const int o = ent_off[wave][k + u];
+                    ww[u] = ent_w[wave][k + u];
 #pragma unroll
                     for (int j = 0; j < LPC; ++j) x[u][j] = Xs[o + lane + 64 * j];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < UN; ++u)
 #pragma unroll
                     for (int j = 0; j < LPC; ++j) {
-                        a1[j] = fma(u1[u], x[u][j], a1[j]);
-                        a2[j] = fma(u2[u], x[u][j], a2[j]);
+                        a1[j] = fma(ww[u].x, x[u][j], a1[j]);
+                        a2[j] = fma(ww[u].y, x[u][j], a2[j]);
                     }
             }
             for (; k < m; ++k) {
-                const int o = __builtin_amdgcn_readlane(off[i], k);
-                const T u1 = bcast(wa[i], k), u2 = bcast(wb[i], k);
+                const int o = ent_off[wave][k];
+                const P2 ww = ent_w[wave][k];
 #pragma unroll
                 for (int j = 0; j < LPC; ++j) {
                     const T x = Xs[o + lane + 64 * j];
-                    a1[j] = fma(u1, x, a1[j]);
-                    a2[j] = fma(u2, x, a2[j]);
+                    a1[j] = fma(ww.x, x, a1[j]);
+                    a2[j] = fma(ww.y, x, a2[j]);
                 }
             }
 #pragma unroll
@@ -822,7 +834,8 @@ size_t spmm_halo_part_doubles(int64_t nb, int p) {
 
 template <typename T>
 hipError_t launch_spmm_halo(hipStream_t s, int mode, int64_t nb, int p, const int64_t *row0, const int64_t *hoff,
-                            const int32_t *halo, const int64_t *rp, const uint16_t *lcol, const void *wv,
+                            const int32_t *halo, const int32_t *rbase, const int64_t *rp, const uint16_t *lcol,
+                            const void *wv,
                             const T *X, T *Y1, T *Y2, int sel, const T *lam, const uint8_t *active, double *part,
                             size_t part_capacity, int *rows_out) {
     using P2 = typename pair_t<T>::type;
@@ -831,14 +844,14 @@ hipError_t launch_spmm_halo(hipStream_t s, int mode, int64_t nb, int p, const in
     if (nbp <= 0 || nbp > 0x7fffffff) return hipErrorInvalidValue;
     if (mode == 0) {
         hipLaunchKernelGGL((k_spmm_halo<T, 0>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff,
-                           halo, rp, lcol, w, X, Y1, Y2, sel, lam, active, part);
+                           halo, rbase, rp, lcol, w, X, Y1, Y2, sel, lam, active, part);
         return hipGetLastError();
     }
     const int64_t ng = (nbp + HALO_G - 1) / HALO_G;
     if ((size_t)(ng + nbp) * p > part_capacity) return hipErrorInvalidValue;
     double *bpart = part + ng * p;
     hipLaunchKernelGGL((k_spmm_halo<T, 1>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff, halo,
-                       rp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
+                       rbase, rp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
     *rows_out = (int)ng;
     return hipGetLastError();
 }
@@ -851,11 +864,13 @@ hipError_t launch_halo_part_rows(hipStream_t s, int64_t nb, int p, double *part)
 }
 
 template hipError_t launch_spmm_halo<double>(hipStream_t, int, int64_t, int, const int64_t *, const int64_t *,
-                                             const int32_t *, const int64_t *, const uint16_t *, const void *,
+                                             const int32_t *, const int32_t *, const int64_t *, const uint16_t *,
+                                             const void *,
                                              const double *, double *, double *, int, const double *,
                                              const uint8_t *, double *, size_t, int *);
 template hipError_t launch_spmm_halo<float>(hipStream_t, int, int64_t, int, const int64_t *, const int64_t *,
-                                            const int32_t *, const int64_t *, const uint16_t *, const void *,
+                                            const int32_t *, const int32_t *, const int64_t *, const uint16_t *,
+                                            const void *,
                                             const float *, float *, float *, int, const float *, const uint8_t *,
                                             double *, size_t, int *);
 int halo_max_rows() { return HALO_MAX; }

@@ -44,8 +44,8 @@ hipError_t launch_spmv_dot(hipStream_t, int, int64_t, const int64_t *, const int
                            const double *, double *, double *);
 template <typename T>
 hipError_t launch_spmm_halo(hipStream_t, int, int64_t, int, const int64_t *, const int64_t *, const int32_t *,
-                            const int64_t *, const uint16_t *, const void *, const T *, T *, T *, int, const T *,
-                            const uint8_t *, double *, size_t, int *);
+                            const int32_t *, const int64_t *, const uint16_t *, const void *, const T *, T *, T *, int,
+                            const T *, const uint8_t *, double *, size_t, int *);
 size_t spmm_halo_part_doubles(int64_t nb, int p);
 hipError_t launch_halo_part_rows(hipStream_t, int64_t, int, double *);
 int halo_max_rows();
@@ -205,6 +205,7 @@ struct ofks_ctx {
     int64_t halo_nb = 0;                  // 0: no plan (a row alone exceeds the halo capacity)
     int64_t *halo_row0 = nullptr, *halo_off = nullptr;
     int32_t *halo_idx = nullptr;
+    int32_t *halo_rbase = nullptr;        // per block: halo slot of its first row
     uint16_t *halo_lcol = nullptr;
 
     // SCF work
@@ -528,7 +529,7 @@ int spmm_pair(ofks_ctx *c, int p, const void *w, const T *X, T *Y1, T *Y2, int s
     const int h = halo_choice(c, p, sizeof(T));
     if (h < 0) return fail(c, OFKS_ESTATE, "spmm_mode halo: no halo plan for this matrix");
     if (h)
-        HIPCHK(launch_spmm_halo<T>(c->stream, 0, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->rp,
+        HIPCHK(launch_spmm_halo<T>(c->stream, 0, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->halo_rbase, c->rp,
                                    c->halo_lcol, w, X, Y1, Y2, sel, nullptr, nullptr, nullptr, 0, nullptr));
     else
         HIPCHK(launch_spmm_pair<T>(c->stream, c->n, p, c->rp, c->col, w, X, Y1, Y2, sel));
@@ -546,7 +547,7 @@ int spmm_shift(ofks_ctx *c, int p, const void *lb, const T *lam, const uint8_t *
         CHK(ensure_part(c, spmm_halo_part_doubles(c->halo_nb, p)));
         {
             Scope sc(c, "spmm_shift");
-            HIPCHK(launch_spmm_halo<T>(c->stream, 1, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->rp,
+            HIPCHK(launch_spmm_halo<T>(c->stream, 1, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->halo_rbase, c->rp,
                                        c->halo_lcol, lb, D, Q, nullptr, 0, lam, act, c->part, c->part_cap, used));
         }
         HIPCHK(launch_halo_part_rows(c->stream, c->halo_nb, p, c->part));
@@ -1041,6 +1042,7 @@ void free_halo(ofks_ctx *c) {
     dfree(c, c->halo_row0);
     dfree(c, c->halo_off);
     dfree(c, c->halo_idx);
+    dfree(c, c->halo_rbase);
     dfree(c, c->halo_lcol);
     c->halo_nb = 0;
 }
@@ -1072,12 +1074,14 @@ int build_halo_plan(ofks_ctx *c) {
     CHK(dalloc(c, &c->halo_row0, nb + 1));
     CHK(dalloc(c, &c->halo_off, nb + 1));
     CHK(dalloc(c, &c->halo_idx, P.halo.size()));
+    CHK(dalloc(c, &c->halo_rbase, nb));
     CHK(dalloc(c, &c->halo_lcol, nnz));
     HIPCHK(hipMemcpyAsync(c->halo_row0, P.row0.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_off, P.hoff.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_idx, P.halo.data(), P.halo.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_lcol, P.lcol.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->halo_rbase, P.rbase.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->halo_nb = nb;
     return OFKS_OK;

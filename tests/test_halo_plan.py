@@ -1,9 +1,10 @@
 """Host logic of the LDS-halo SpMM: the row-block plan (csrc/halo_plan.hpp),
 compiled here with g++ and checked from outside on real and adversarial CSR
 patterns.  What the plan must satisfy: every row in exactly one block of
-consecutive rows, at most rmax rows and hmax distinct columns per block, the
-halo sorted and equal to the block's column set, every entry's slot pointing
-back to its own column, and greedy blocks (the next row would not have fit)."""
+consecutive rows, at most rmax rows per block, the halo sorted and equal to
+the block's columns together with its rows (at most hmax), the rows at
+consecutive slots from rbase, every entry's slot pointing back to its own
+column, and greedy blocks (the next row would not have fit)."""
 import os
 import shutil
 import subprocess
@@ -40,6 +41,7 @@ int main(int argc, char **argv) {
     std::fwrite(&nb, 8, 1, g); std::fwrite(&hl, 8, 1, g); std::fwrite(&nl, 8, 1, g);
     std::fwrite(P.row0.data(), 8, P.row0.size(), g); std::fwrite(P.hoff.data(), 8, P.hoff.size(), g);
     std::fwrite(P.halo.data(), 4, hl, g); std::fwrite(P.lcol.data(), 2, nl, g);
+    std::fwrite(P.rbase.data(), 4, P.rbase.size(), g);
     std::fclose(g);
     return 0;
 }
@@ -72,9 +74,10 @@ def planner(tmp_path_factory):
         row0 = np.frombuffer(b[o:o + 8 * (nb + 1)], np.int64); o += 8 * (nb + 1)
         hoff = np.frombuffer(b[o:o + 8 * (nb + 1)], np.int64); o += 8 * (nb + 1)
         halo = np.frombuffer(b[o:o + 4 * hl], np.int32); o += 4 * hl
-        lcol = np.frombuffer(b[o:o + 2 * nl], np.uint16)
+        lcol = np.frombuffer(b[o:o + 2 * nl], np.uint16); o += 2 * nl
+        rbase = np.frombuffer(b[o:o + 4 * nb], np.int32)
         return dict(rc=int(rc), rc2=int(rc2), where=int(where), nb=int(nb), row0=row0, hoff=hoff, halo=halo,
-                    lcol=lcol)
+                    lcol=lcol, rbase=rbase)
     return run
 
 
@@ -82,18 +85,19 @@ def _check_plan(P, rp, col, hmax, rmax, emax=64):
     n = len(rp) - 1
     assert P["rc"] == 0 and P["rc2"] == 0
     assert np.diff(rp).max() <= emax
-    row0, hoff, halo, lcol = P["row0"], P["hoff"], P["halo"], P["lcol"]
+    row0, hoff, halo, lcol, rbase = P["row0"], P["hoff"], P["halo"], P["lcol"], P["rbase"]
     assert row0[0] == 0 and row0[-1] == n and np.all(np.diff(row0) >= 1) and np.all(np.diff(row0) <= rmax)
     assert hoff[0] == 0 and hoff[-1] == len(halo)
     for b in range(P["nb"]):
         r0, r1 = row0[b], row0[b + 1]
         cols = col[rp[r0]:rp[r1]]
         h = halo[hoff[b]:hoff[b + 1]]
-        assert np.array_equal(h, np.unique(cols))              # sorted, exactly the block's columns
+        assert np.array_equal(h, np.union1d(cols, np.arange(r0, r1)))   # sorted: the columns and the rows
         assert len(h) <= hmax
         assert np.array_equal(h[lcol[rp[r0]:rp[r1]]], cols)    # every slot maps back
+        assert np.array_equal(h[rbase[b]:rbase[b] + (r1 - r0)], np.arange(r0, r1))
         if r1 < n:                                             # greedy: the next row would not fit
-            nxt = np.union1d(h, col[rp[r1]:rp[r1 + 1]])
+            nxt = np.union1d(h, np.append(col[rp[r1]:rp[r1 + 1]], r1))
             assert r1 - r0 == rmax or len(nxt) > hmax
 
 
@@ -108,6 +112,10 @@ def test_plan_on_fem_pattern(planner):
     rows = np.diff(P["row0"])
     hal = np.diff(P["hoff"])
     assert hal.sum() < 0.5 * d.nnz and rows.mean() > 8
+    # every FEM row has its diagonal: adding the rows changes no halo
+    for b in range(P["nb"]):
+        r0, r1 = P["row0"][b], P["row0"][b + 1]
+        assert hal[b] == len(np.unique(d.col[d.row_ptr[r0]:d.row_ptr[r1]]))
 
 
 def test_plan_on_random_patterns(planner):
@@ -123,14 +131,14 @@ def test_plan_on_random_patterns(planner):
 
 
 def test_plan_with_empty_rows(planner):
-    # 100 empty rows first (a block with an empty halo), then a band matrix
+    # 100 empty rows first (blocks whose halo is just their rows), then a band matrix
     n = 400
     lens = np.concatenate([np.zeros(100, np.int64), np.full(n - 100, 3)])
     rp = np.concatenate([[0], np.cumsum(lens)])
     col = np.concatenate([[max(r - 1, 100), r, min(r + 1, n - 1)] for r in range(100, n)]).astype(np.int32)
     P = planner(rp, col)
     _check_plan(P, rp, col, 160, 64)
-    assert P["hoff"][1] == 0                      # rows 0..63: empty halo
+    assert P["hoff"][1] == 64 and P["rbase"][0] == 0   # rows 0..63: the halo is the rows
 
 
 def test_plan_refuses_too_wide_rows_and_bad_indices(planner):
