@@ -443,15 +443,17 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 // ---------------------------------------------------------------------------
 // LDS-halo SpMM.  Block b owns the consecutive rows [row0[b], row0[b+1]) (at
 // most HALO_RMAX, each with at most 64 entries) and their halo: the distinct
-// columns of those rows, halo[hoff[b] .. hoff[b+1]) in ascending order (at
-// most HALO_MAX rows of X).  lcol[e] is the halo slot of CSR entry e.
-// Wave v of the block takes rows row0[b] + v + 8 i; it loads their entries
-// (slot, weight pair) once, one entry per lane, and keeps them in registers.
-// For each 512-byte slice of the columns the block stages its halo rows of X
-// in LDS, then every wave forms its rows from LDS, broadcasting the entries
-// with readlane.  X is gathered from L2 about (halo size / rows) times instead
-// of once per nonzero, and consecutive blocks (one XCD's slab, in dispatch
-// order) share their halos in that XCD's L2.
+// columns of those rows together with the rows themselves, halo[hoff[b] ..
+// hoff[b+1]) in ascending order (at most HALO_MAX rows of X), so the block's
+// rows sit at slots rbase[b], rbase[b] + 1, ...  lcol[e] is the halo slot of
+// CSR entry e.  Wave v of the block takes rows row0[b] + v + HALO_WAVES i; it
+// loads their entries (slot, weight pair) once, one entry per lane, and keeps
+// them in registers.  For each 512-byte slice of the columns the block stages
+// its halo rows of X in LDS; every wave then forms its rows from LDS, reading
+// each row's entries back from a per-wave LDS area at uniform addresses (an
+// LDS broadcast).  X is gathered from L2 about (halo size / rows) times
+// instead of once per nonzero, and consecutive blocks (one XCD's slab, in
+// dispatch order) share their halos in that XCD's L2.
 //  MODE 0: Y1 = A1 X and Y2 = A2 X (or, Y2 = NULL, A1 X or A2 X by sel).
 //  MODE 1: Y1 = Q = (A1 - lam_c A2) D on active columns (0 elsewhere), and
 //          part[b][c] = <D_c, Q_c> over the block's rows.
@@ -475,14 +477,6 @@ constexpr int HALO_MAX = OFKS_HALO_MAX, HALO_RMAX = OFKS_HALO_RMAX, HALO_WAVES =
 constexpr int HALO_RPW = HALO_RMAX / HALO_WAVES;   // rows per wave
 static_assert(HALO_RMAX % HALO_WAVES == 0, "whole rows per wave");
 
-__device__ __forceinline__ double bcast(double v, int k) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float bcast(float v, int k) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
 
 // the register cap keeps every block the LDS admits resident
 template <typename T, int MODE>
