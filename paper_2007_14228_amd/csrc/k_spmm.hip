@@ -519,14 +519,11 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
     constexpr int SPT = (HALO_MAX + SST - 1) / SST;
     static_assert((64 * HALO_WAVES) % SEG == 0, "whole slot rows per pass");
     const int sg = threadIdx.x % SEG, ss = threadIdx.x / SEG;
-    // (slots past the halo re-read its last row, never stored; a halo can be
-    // empty only for a block of empty rows)
+    // (a halo holds at least the block's rows; slots past it re-read its last
+    // row and are never stored)
     int hrow[SPT];
 #pragma unroll
-    for (int u = 0; u < SPT; ++u) {
-        const int64_t hi = hn > 0 ? h0 + min(ss + SST * u, hn - 1) : 0;   // entry 0 is always allocated
-        hrow[u] = halo[hi];
-    }
+    for (int u = 0; u < SPT; ++u) hrow[u] = halo[h0 + min(ss + SST * u, hn - 1)];
     // this wave's rows: entry k of row i sits in lane k (lanes past the row
     // re-read entry 0, which every allocation holds, and are never used)
     int len[HALO_RPW], off[HALO_RPW];

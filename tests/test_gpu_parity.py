@@ -117,6 +117,24 @@ def test_preconditioner_cg(p, mode, graded):
     assert _relerr(P, ref) < 1e-11
 
 
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+def test_products_are_bitwise_repeatable(mode, graded):
+    """Fixed-order reductions: the same call twice gives the same bits (the
+    dual product, and the preconditioner whose CG sums per-block partials)."""
+    w, d = graded
+    p = 130
+    print(f"[gpu] repeatability mode={mode}", flush=True)
+    s = _solver_for(w)
+    s.set_params(precond="paper", pcg_iters=10, spmm_mode=mode)
+    rng = np.random.default_rng(21)
+    X = _dev(rng.standard_normal((d.n, p)))
+    lam = -np.abs(rng.standard_normal(p)) - 0.1
+    a = [_host(t) for t in s.spmm(X)] + [_host(s.precondition(lam, X))]
+    b = [_host(t) for t in s.spmm(X)] + [_host(s.precondition(lam, X))]
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
 def test_matrix_without_halo_plan_uses_row_gather():
     """csr_load of a pattern with a row wider than the LDS halo: no halo plan,
     the automatic choice takes the row-gather kernel, a forced halo kernel is
