@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 #define OFKS_HALO_MAX 80
 #endif
 #ifndef OFKS_HALO_RMAX
-#define OFKS_HALO_RMAX 32
+#define OFKS_HALO_RMAX 16   // an 80-row halo holds about 16 Morton-ordered rows' neighbours anyway
 #endif
 #ifndef OFKS_HALO_WAVES
 #define OFKS_HALO_WAVES 8
@@ -597,9 +597,7 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
             ent_off[wave][lane] = off[i];
             ent_w[wave][lane] = P2{wa[i], wb[i]};
             __builtin_amdgcn_wave_barrier();
-            // entries in flight per step (the FP64 shifted product holds more
-            // state per lane, so it takes two to stay within its registers)
-            constexpr int UN = (MODE == 1 && sizeof(T) == 8) ? 2 : 4;
+            constexpr int UN = 4;   // entries in flight per step
             int k = 0;
             for (; k + UN <= m; k += UN) {
                 T x[UN][LPC];
