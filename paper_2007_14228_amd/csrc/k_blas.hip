@@ -247,7 +247,8 @@ __global__ __launch_bounds__(256) void k_rowgemm(int64_t n, int p, int N, const 
 // Block: 4 waves, 64 rows x TC = 16 NTW columns; wave w owns rows 16w..16w+15
 // of the tile and all NTW 16x16 output tiles.  A (scaled by sa) and M are
 // staged through LDS in K-chunks of 16 (zero-filled past p, N and n), so any
-// shape works.  Operand layout of the 16x16x4 instructions (lane l, measured
+// shape works; the next chunk's values are loaded into registers while the
+// current chunk's MFMAs run.  Operand layout of the 16x16x4 instructions (lane l, measured
 // on gfx950): A[l % 16][l / 16], B[l / 16][l % 16]; result slot i < 4 holds
 // D[4 (l / 16) + i][l % 16] for f32 and D[l / 16 + 4 i][l % 16] for f64.
 // Epilogues and per-block partials as in k_rowgemm.
