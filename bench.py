@@ -47,7 +47,43 @@ def parse():
                     help="also run FP64 and mixed precision to this residual and report the energy difference")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (known bytes) for HBM counter calibration")
+    ap.add_argument("--study-steps", default=None, metavar="A:B",
+                    help="also run FP64 to residual 1e-6 for workload seeds A..B-1 under each step rule (BB2, BB1, "
+                         "ABB1, ABB2) with the paper preconditioner, and BB2 without one; report iterations")
     return ap.parse_args()
+
+
+def step_rule_study(torch, a, params):
+    """Section 4.4's comparison of the BB step rules (and Section 5's check
+    that the preconditioner helps) on seeded workloads of one kind: FP64, same
+    X0 per seed, residual 1e-6, iterations and seconds per (rule, preconditioner)."""
+    import workloads as wl
+    from paper_2007_14228_amd import Solver
+    lo, hi = (int(v) for v in a.study_steps.split(":"))
+    cases = [("bb2", "paper"), ("bb1", "paper"), ("abb1", "paper"), ("abb2", "paper"), ("bb2", "none")]
+    runs = []
+    for seed in range(lo, hi):
+        w = wl.make_workload(a.workload, seed=seed)
+        X0 = torch.from_numpy(wl.random_block(1000 + seed, w.mesh.n_dofs, w.p)).to("cuda")
+        s = Solver()
+        s.load_workload(w)
+        for rule, pre in cases:
+            r = run_to_tol(torch, s, X0, 1e-6, dict(params, beta=w.beta, scf=1 if w.scf else 0, step_rule=rule,
+                                                    precond=pre))
+            log(f"  seed {seed} {rule}/{pre}: {r['iterations']} iterations, {r['seconds']} s, rel {r['rel']:.2e}")
+            runs.append(dict(seed=seed, step_rule=rule, precond=pre, iterations=r["iterations"],
+                             seconds=r["seconds"], converged=r["converged"], rel=r["rel"], energy=r["energy"]))
+        s.close()
+    summary = {}
+    for rule, pre in cases:
+        rs = [r for r in runs if r["step_rule"] == rule and r["precond"] == pre]
+        conv = [r for r in rs if r["converged"]]
+        summary[f"{rule}/{pre}"] = dict(
+            converged=f"{len(conv)}/{len(rs)}",
+            median_iterations=float(np.median([r["iterations"] for r in conv])) if conv else None,
+            mean_seconds=round(float(np.mean([r["seconds"] for r in conv])), 3) if conv else None)
+    return dict(workload=a.workload, seeds=f"{lo}:{hi}", tol=1e-6, max_iter=params["max_iter"], runs=runs,
+                summary=summary)
 
 
 def log(msg):
@@ -265,6 +301,9 @@ def main():
         ttr["speedup_vs_fp64_paper"] = {k: round(plain["seconds"] / v["seconds"], 3)
                                         for k, v in ttr.items() if k != "fp64_paper_precond" and v.get("converged")}
         out["time_to_residual_1e-6"] = ttr
+    if a.study_steps:
+        log(f"step-rule study, {a.workload} seeds {a.study_steps}")
+        out["step_rule_study"] = step_rule_study(torch, a, params)
     if a.energy_check > 0:
         # the precision form's energy error, both runs converged well past 1e-6
         tol = a.energy_check
