@@ -50,7 +50,42 @@ def parse():
     ap.add_argument("--study-steps", default=None, metavar="A:B",
                     help="also run FP64 to residual 1e-6 for workload seeds A..B-1 under each step rule (BB2, BB1, "
                          "ABB1, ABB2) with the paper preconditioner, and BB2 without one; report iterations")
+    ap.add_argument("--study-p", default=None, metavar="P1,P2,...",
+                    help="also time FP64 iterations of the same workload at these block widths and report each "
+                         "kernel's share of an iteration")
     return ap.parse_args()
+
+
+P_STUDY_TIMERS = ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_r", "pcg_dx", "bbdot", "density",
+                  "poisson", "assemble_h")
+
+
+def p_study(torch, a, s, w, params, steps=3, warmup=2):
+    """Per-kernel share of an FP64 iteration against the block width p at a
+    fixed mesh (the single-GPU analogue of the paper's per-part cost figure)."""
+    import workloads as wl
+    n = w.mesh.n_dofs
+    rows = []
+    for p in (int(v) for v in a.study_p.split(",")):
+        X0 = torch.from_numpy(wl.random_block(2000 + p, n, p)).to("cuda")
+        s.set_params(tol=1e-30, **dict(params, max_iter=warmup + steps + 5, energy_every=10 if p > 64 else 1))
+        s.set_x0(X0, orthonormalize=True)
+        del X0
+        s.step(warmup)
+        s.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _, _ = s.step(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / len(st)
+        ms = {k: s.timer(k)[0] / len(st) for k in P_STUDY_TIMERS}
+        s.timing(False)
+        ms = {k: round(v, 3) for k, v in ms.items() if v > 0}
+        share = {k: round(v / (dt * 1e3), 3) for k, v in ms.items()}
+        log(f"  p={p}: {dt * 1e3:.1f} ms/iteration; " + " ".join(f"{k}={v:.0%}" for k, v in share.items()))
+        rows.append(dict(p=p, ms_per_iteration=round(dt * 1e3, 3), kernel_ms=ms, share=share))
+    return dict(workload=a.workload, n=n, precision="f64", precond=params["precond"], pcg_iters=params["pcg_iters"],
+                rows=rows)
 
 
 def step_rule_study(torch, a, params):
@@ -301,6 +336,9 @@ def main():
         ttr["speedup_vs_fp64_paper"] = {k: round(plain["seconds"] / v["seconds"], 3)
                                         for k, v in ttr.items() if k != "fp64_paper_precond" and v.get("converged")}
         out["time_to_residual_1e-6"] = ttr
+    if a.study_p:
+        log(f"block-width study, {a.workload}: p = {a.study_p}")
+        out["p_study"] = p_study(torch, a, s, w, params)
     if a.study_steps:
         log(f"step-rule study, {a.workload} seeds {a.study_steps}")
         out["step_rule_study"] = step_rule_study(torch, a, params)
