@@ -301,9 +301,10 @@ hipError_t launch_cg_start(hipStream_t s, int grid, int64_t n, double scale, con
     hipLaunchKernelGGL(k_cg_reduce3, dim3(1), dim3(256), 0, s, grid, part, sc);
     return hipGetLastError();
 }
-hipError_t launch_cg_xr(hipStream_t s, int grid, int64_t n, int parity, double *sc, const double *dq,
+// nb_dq: the number of <d, q> partials (the product's grid)
+hipError_t launch_cg_xr(hipStream_t s, int grid, int64_t n, int parity, double *sc, int nb_dq, const double *dq,
                         const double *d, const double *q, const double *dg, double *x, double *r, double *part) {
-    hipLaunchKernelGGL(k_cg_xr, dim3(grid), dim3(256), 0, s, n, parity, sc, grid, dq, d, q, dg, x, r, part);
+    hipLaunchKernelGGL(k_cg_xr, dim3(grid), dim3(256), 0, s, n, parity, sc, nb_dq, dq, d, q, dg, x, r, part);
     return hipGetLastError();
 }
 

@@ -142,8 +142,8 @@ hipError_t launch_veff(hipStream_t, int64_t, const int32_t *, const int32_t *, c
                        const double *, double *);
 hipError_t launch_cg_start(hipStream_t, int, int64_t, double, const double *, const double *, const double *,
                            double *, double *, double *, double *);
-hipError_t launch_cg_xr(hipStream_t, int, int64_t, int, double *, const double *, const double *, const double *,
-                        const double *, double *, double *, double *);
+hipError_t launch_cg_xr(hipStream_t, int, int64_t, int, double *, int, const double *, const double *,
+                        const double *, const double *, double *, double *, double *);
 hipError_t launch_cg_dir(hipStream_t, int, int64_t, int, double *, const double *, const double *, const double *,
                          double *);
 hipError_t launch_dot(hipStream_t, int, int64_t, const double *, const double *, double *);
@@ -574,7 +574,13 @@ template <typename T> int coldot(ofks_ctx *c, const T *A, const T *B, std::vecto
 // Hartree CG grid: enough 256-thread blocks to fill the device (the vectors
 // are short, so the kernels are latency-bound); the fused reductions sum one
 // partial per block.
-constexpr int CG_BLOCKS = 2048;
+#ifndef OFKS_CG_SPMV_BLOCKS
+#define OFKS_CG_SPMV_BLOCKS 2048   // the Hartree SpMV's grid
+#endif
+#ifndef OFKS_CG_UPD_BLOCKS
+#define OFKS_CG_UPD_BLOCKS 512     // the CG vector updates' grid: each of their blocks sums all the previous
+#endif                             // kernel's partials, so fewer blocks read far fewer (measured at n = 2e5)
+constexpr int CG_BLOCKS = OFKS_CG_SPMV_BLOCKS;
 
 void drop_cg_graph(ofks_ctx *c) {
     if (c->cg_graph) (void)hipGraphExecDestroy(c->cg_graph);
@@ -583,13 +589,14 @@ void drop_cg_graph(ofks_ctx *c) {
 
 int poisson(ofks_ctx *c) {
     const int64_t n = c->n;
-    const int g = CG_BLOCKS;                    // blocks; partials: <d, q> then 3-wide update sums
+    const int g = CG_BLOCKS, gu = OFKS_CG_UPD_BLOCKS;   // partials: <d, q> (g), then 3-wide update sums (gu)
+    static_assert(OFKS_CG_UPD_BLOCKS <= CG_BLOCKS, "partial buffer sized for CG_BLOCKS");
     double *dqp = c->cg_part, *xrp = c->cg_part + g;
     {
         Scope sc(c, "poisson");
         HIPCHK(launch_spmv_dot(c->stream, g, n, c->rp, c->col, c->Lv, c->U, c->cg_q, dqp));
         // Jacobi preconditioner diag(L/2): a constant multiple of diag(L) leaves the CG iterates unchanged
-        HIPCHK(launch_cg_start(c->stream, g, n, 4.0 * M_PI, c->bvec, c->cg_q, c->lhd, c->cg_r, c->cg_d, xrp,
+        HIPCHK(launch_cg_start(c->stream, gu, n, 4.0 * M_PI, c->bvec, c->cg_q, c->lhd, c->cg_r, c->cg_d, xrp,
                                c->cg_sc));
     }
     std::vector<double> sc;
@@ -602,10 +609,10 @@ int poisson(ofks_ctx *c) {
         for (int j = 0; j < 10; ++j) {
             hipError_t e;
             if ((e = launch_spmv_dot(s, g, n, c->rp, c->col, c->Lv, c->cg_d, c->cg_q, dqp)) != hipSuccess) return e;
-            if ((e = launch_cg_xr(s, g, n, j & 1, c->cg_sc, dqp, c->cg_d, c->cg_q, c->lhd, c->U, c->cg_r, xrp)) !=
+            if ((e = launch_cg_xr(s, gu, n, j & 1, c->cg_sc, g, dqp, c->cg_d, c->cg_q, c->lhd, c->U, c->cg_r, xrp)) !=
                 hipSuccess)
                 return e;
-            if ((e = launch_cg_dir(s, g, n, j & 1, c->cg_sc, xrp, c->cg_r, c->lhd, c->cg_d)) != hipSuccess) return e;
+            if ((e = launch_cg_dir(s, gu, n, j & 1, c->cg_sc, xrp, c->cg_r, c->lhd, c->cg_d)) != hipSuccess) return e;
         }
         return hipSuccess;
     };
