@@ -443,9 +443,10 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 // ---------------------------------------------------------------------------
 // LDS-halo SpMM.  Block b owns the consecutive rows [row0[b], row0[b+1]) (at
 // most HALO_RMAX, each with at most 64 entries) and their halo: the distinct
-// columns of those rows together with the rows themselves, halo[hoff[b] ..
-// hoff[b+1]) in ascending order (at most HALO_MAX rows of X), so the block's
-// rows sit at slots rbase[b], rbase[b] + 1, ...  lcol[e] is the halo slot of
+// columns of those rows together with the rows themselves in ascending order,
+// hoff[b+1] - hoff[b] <= HALO_MAX rows of X listed at halo[b HALO_STRIDE ...]
+// (padded to the stride with the last one), so the block's rows sit at slots
+// rbase[b], rbase[b] + 1, ...  lcol[e] is the halo slot of
 // CSR entry e.  Wave v of the block takes rows row0[b] + v + HALO_WAVES i; it
 // loads their entries (slot, weight pair) once, one entry per lane, and keeps
 // them in registers.  For each 512-byte slice of the columns the block stages
@@ -475,6 +476,12 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 #endif
 constexpr int HALO_MAX = OFKS_HALO_MAX, HALO_RMAX = OFKS_HALO_RMAX, HALO_WAVES = OFKS_HALO_WAVES, HALO_EMAX = 64;
 constexpr int HALO_RPW = HALO_RMAX / HALO_WAVES;   // rows per wave
+// Each block's halo row list is padded to HALO_STRIDE entries (repeating its
+// last row), so its address depends on the block index alone: the staging
+// threads' row lookups need no offset load first.  Both precisions stage
+// 32 sixteen-byte segments per slot, HALO_SST slots per pass.
+constexpr int HALO_SST = 64 * HALO_WAVES / 32;
+constexpr int HALO_STRIDE = (HALO_MAX + HALO_SST - 1) / HALO_SST * HALO_SST;
 static_assert(HALO_RMAX % HALO_WAVES == 0, "whole rows per wave");
 
 
@@ -518,12 +525,13 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
     constexpr int SST = 64 * HALO_WAVES / SEG;
     constexpr int SPT = (HALO_MAX + SST - 1) / SST;
     static_assert((64 * HALO_WAVES) % SEG == 0, "whole slot rows per pass");
+    static_assert(SST == HALO_SST && SPT * SST == HALO_STRIDE, "padded halo stride");
     const int sg = threadIdx.x % SEG, ss = threadIdx.x / SEG;
-    // (a halo holds at least the block's rows; slots past it re-read its last
+    // (halo is padded per block; slots past the block's halo repeat its last
     // row and are never stored)
     int hrow[SPT];
 #pragma unroll
-    for (int u = 0; u < SPT; ++u) hrow[u] = halo[h0 + min(ss + SST * u, hn - 1)];
+    for (int u = 0; u < SPT; ++u) hrow[u] = halo[b * HALO_STRIDE + ss + SST * u];
     // this wave's rows: entry k of row i sits in lane k (lanes past the row
     // re-read entry 0, which every allocation holds, and are never used)
     int len[HALO_RPW], off[HALO_RPW];
@@ -865,6 +873,7 @@ template hipError_t launch_spmm_halo<float>(hipStream_t, int, int64_t, int, cons
 int halo_max_rows() { return HALO_MAX; }
 int halo_max_block_rows() { return HALO_RMAX; }
 int halo_max_row_entries() { return HALO_EMAX; }
+int halo_pad_stride() { return HALO_STRIDE; }
 
 template hipError_t launch_spmm_pair<double>(hipStream_t, int64_t, int, const int64_t *, const int32_t *,
                                              const void *, const double *, double *, double *, int);

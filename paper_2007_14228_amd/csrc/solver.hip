@@ -51,6 +51,7 @@ hipError_t launch_halo_part_rows(hipStream_t, int64_t, int, double *);
 int halo_max_rows();
 int halo_max_block_rows();
 int halo_max_row_entries();
+int halo_pad_stride();
 // (k_blas.hip)
 struct GradArgs {
     const void *HX;
@@ -204,7 +205,7 @@ struct ofks_ctx {
     // columns (halo) and each entry's slot in its block's halo
     int64_t halo_nb = 0;                  // 0: no plan (a row alone exceeds the halo capacity)
     int64_t *halo_row0 = nullptr, *halo_off = nullptr;
-    int32_t *halo_idx = nullptr;
+    int32_t *halo_idx = nullptr;          // per block: its halo rows, padded to a fixed stride
     int32_t *halo_rbase = nullptr;        // per block: halo slot of its first row
     uint16_t *halo_lcol = nullptr;
 
@@ -1081,12 +1082,19 @@ int build_halo_plan(ofks_ctx *c) {
     const int64_t nb = P.nb();
     CHK(dalloc(c, &c->halo_row0, nb + 1));
     CHK(dalloc(c, &c->halo_off, nb + 1));
-    CHK(dalloc(c, &c->halo_idx, P.halo.size()));
+    // the kernel reads each block's halo rows at a fixed stride, padded with its last row
+    const int HS = halo_pad_stride();
+    std::vector<int32_t> hpad((size_t)nb * HS);
+    for (int64_t k = 0; k < nb; ++k) {
+        const int64_t h0 = P.hoff[k], hn = P.hoff[k + 1] - h0;   // 1 <= hn <= HS (the plan check)
+        for (int s = 0; s < HS; ++s) hpad[(size_t)k * HS + s] = P.halo[h0 + std::min<int64_t>(s, hn - 1)];
+    }
+    CHK(dalloc(c, &c->halo_idx, hpad.size()));
     CHK(dalloc(c, &c->halo_rbase, nb));
     CHK(dalloc(c, &c->halo_lcol, nnz));
     HIPCHK(hipMemcpyAsync(c->halo_row0, P.row0.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_off, P.hoff.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->halo_idx, P.halo.data(), P.halo.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+    HIPCHK(hipMemcpyAsync(c->halo_idx, hpad.data(), hpad.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_lcol, P.lcol.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_rbase, P.rbase.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
