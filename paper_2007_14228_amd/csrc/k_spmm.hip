@@ -446,8 +446,11 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 // columns of those rows together with the rows themselves in ascending order,
 // hoff[b+1] - hoff[b] <= HALO_MAX rows of X listed at halo[b HALO_STRIDE ...]
 // (padded to the stride with the last one), so the block's rows sit at slots
-// rbase[b], rbase[b] + 1, ...  lcol[e] is the halo slot of
-// CSR entry e.  Wave v of the block takes rows row0[b] + v + HALO_WAVES i; it
+// rbase[b], rbase[b] + 1, ...  brp[b HALO_BRP + k] is the CSR row pointer of
+// row row0[b] + k, for k = 0 .. HALO_RMAX (padded with row0[b+1]'s, so rows
+// past the block have no entries).  lcol[e] is the halo slot of CSR entry e.
+// Every per-block address depends on b alone: the block's metadata loads all
+// issue at once instead of one after another.  Wave v of the block takes rows row0[b] + v + HALO_WAVES i; it
 // loads their entries (slot, weight pair) once, one entry per lane, and keeps
 // them in registers.  For each 512-byte slice of the columns the block stages
 // its halo rows of X in LDS; every wave then forms its rows from LDS, reading
@@ -482,6 +485,7 @@ constexpr int HALO_RPW = HALO_RMAX / HALO_WAVES;   // rows per wave
 // 32 sixteen-byte segments per slot, HALO_SST slots per pass.
 constexpr int HALO_SST = 64 * HALO_WAVES / 32;
 constexpr int HALO_STRIDE = (HALO_MAX + HALO_SST - 1) / HALO_SST * HALO_SST;
+constexpr int HALO_BRP = HALO_RMAX + 1;            // per-block row pointer stride
 static_assert(HALO_RMAX % HALO_WAVES == 0, "whole rows per wave");
 
 
@@ -489,7 +493,7 @@ static_assert(HALO_RMAX % HALO_WAVES == 0, "whole rows per wave");
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu(OFKS_HALO_WPE))) void k_spmm_halo(
     int64_t nb, int p, const int64_t *__restrict__ row0, const int64_t *__restrict__ hoff,
-    const int32_t *__restrict__ halo, const int32_t *__restrict__ rbase, const int64_t *__restrict__ rp,
+    const int32_t *__restrict__ halo, const int32_t *__restrict__ rbase, const int64_t *__restrict__ brp,
     const uint16_t *__restrict__ lcol,
     const typename pair_t<T>::type *__restrict__ w, const T *__restrict__ X, T *__restrict__ Y1,
     T *__restrict__ Y2, int sel, const T *__restrict__ lam, const uint8_t *__restrict__ active,
@@ -515,9 +519,6 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
             for (int c = threadIdx.x; c < p; c += blockDim.x) part[b * p + c] = 0.0;
         return;
     }
-    const int64_t r0 = row0[b], r1 = row0[b + 1], h0 = hoff[b];
-    const int hn = (int)(hoff[b + 1] - h0);
-    const int rb = MODE == 1 ? rbase[b] : 0;   // the block's rows sit at halo slots rb, rb + 1, ...
     // 16-byte loads need every row start 16-byte aligned
     const bool vec = p % VW == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
     // staging: thread t always moves 16-byte segment t % SEG of halo slots
@@ -532,15 +533,22 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
     int hrow[SPT];
 #pragma unroll
     for (int u = 0; u < SPT; ++u) hrow[u] = halo[b * HALO_STRIDE + ss + SST * u];
+    // the halo loads go out first; the block's metadata loads below then all
+    // issue together, without the scheduler sinking the halo loads behind them
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t r0 = row0[b], r1 = row0[b + 1];
+    const int hn = (int)(hoff[b + 1] - hoff[b]);
+    const int rb = MODE == 1 ? rbase[b] : 0;   // the block's rows sit at halo slots rb, rb + 1, ...
     // this wave's rows: entry k of row i sits in lane k (lanes past the row
     // re-read entry 0, which every allocation holds, and are never used)
     int len[HALO_RPW], off[HALO_RPW];
     T wa[HALO_RPW], wb[HALO_RPW];
+    const int64_t *bp = brp + b * HALO_BRP;
 #pragma unroll
     for (int i = 0; i < HALO_RPW; ++i) {
-        const int64_t row = r0 + wave + HALO_WAVES * i;
-        const int64_t e0 = row < r1 ? rp[row] : 0;
-        len[i] = row < r1 ? (int)(rp[row + 1] - e0) : 0;
+        const int k = wave + HALO_WAVES * i;
+        const int64_t e0 = bp[k];
+        len[i] = (int)(bp[k + 1] - e0);
         const int64_t e = lane < len[i] ? e0 + lane : 0;
         const P2 ww = w[e];
         off[i] = (int)lcol[e] * CP;
@@ -831,7 +839,7 @@ size_t spmm_halo_part_doubles(int64_t nb, int p) {
 
 template <typename T>
 hipError_t launch_spmm_halo(hipStream_t s, int mode, int64_t nb, int p, const int64_t *row0, const int64_t *hoff,
-                            const int32_t *halo, const int32_t *rbase, const int64_t *rp, const uint16_t *lcol,
+                            const int32_t *halo, const int32_t *rbase, const int64_t *brp, const uint16_t *lcol,
                             const void *wv,
                             const T *X, T *Y1, T *Y2, int sel, const T *lam, const uint8_t *active, double *part,
                             size_t part_capacity, int *rows_out) {
@@ -841,14 +849,14 @@ hipError_t launch_spmm_halo(hipStream_t s, int mode, int64_t nb, int p, const in
     if (nbp <= 0 || nbp > 0x7fffffff) return hipErrorInvalidValue;
     if (mode == 0) {
         hipLaunchKernelGGL((k_spmm_halo<T, 0>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff,
-                           halo, rbase, rp, lcol, w, X, Y1, Y2, sel, lam, active, part);
+                           halo, rbase, brp, lcol, w, X, Y1, Y2, sel, lam, active, part);
         return hipGetLastError();
     }
     const int64_t ng = (nbp + HALO_G - 1) / HALO_G;
     if ((size_t)(ng + nbp) * p > part_capacity) return hipErrorInvalidValue;
     double *bpart = part + ng * p;
     hipLaunchKernelGGL((k_spmm_halo<T, 1>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff, halo,
-                       rbase, rp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
+                       rbase, brp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
     *rows_out = (int)ng;
     return hipGetLastError();
 }
@@ -874,6 +882,7 @@ int halo_max_rows() { return HALO_MAX; }
 int halo_max_block_rows() { return HALO_RMAX; }
 int halo_max_row_entries() { return HALO_EMAX; }
 int halo_pad_stride() { return HALO_STRIDE; }
+int halo_row_ptr_stride() { return HALO_BRP; }
 
 template hipError_t launch_spmm_pair<double>(hipStream_t, int64_t, int, const int64_t *, const int32_t *,
                                              const void *, const double *, double *, double *, int);

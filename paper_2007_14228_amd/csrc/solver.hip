@@ -52,6 +52,7 @@ int halo_max_rows();
 int halo_max_block_rows();
 int halo_max_row_entries();
 int halo_pad_stride();
+int halo_row_ptr_stride();
 // (k_blas.hip)
 struct GradArgs {
     const void *HX;
@@ -207,6 +208,7 @@ struct ofks_ctx {
     int64_t *halo_row0 = nullptr, *halo_off = nullptr;
     int32_t *halo_idx = nullptr;          // per block: its halo rows, padded to a fixed stride
     int32_t *halo_rbase = nullptr;        // per block: halo slot of its first row
+    int64_t *halo_brp = nullptr;          // per block: its rows' CSR row pointers, padded to a fixed stride
     uint16_t *halo_lcol = nullptr;
 
     // SCF work
@@ -531,8 +533,8 @@ int spmm_pair(ofks_ctx *c, int p, const void *w, const T *X, T *Y1, T *Y2, int s
     const int h = halo_choice(c, p, sizeof(T));
     if (h < 0) return fail(c, OFKS_ESTATE, "spmm_mode halo: no halo plan for this matrix");
     if (h)
-        HIPCHK(launch_spmm_halo<T>(c->stream, 0, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->halo_rbase, c->rp,
-                                   c->halo_lcol, w, X, Y1, Y2, sel, nullptr, nullptr, nullptr, 0, nullptr));
+        HIPCHK(launch_spmm_halo<T>(c->stream, 0, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->halo_rbase,
+                                   c->halo_brp, c->halo_lcol, w, X, Y1, Y2, sel, nullptr, nullptr, nullptr, 0, nullptr));
     else
         HIPCHK(launch_spmm_pair<T>(c->stream, c->n, p, c->rp, c->col, w, X, Y1, Y2, sel));
     return OFKS_OK;
@@ -549,8 +551,9 @@ int spmm_shift(ofks_ctx *c, int p, const void *lb, const T *lam, const uint8_t *
         CHK(ensure_part(c, spmm_halo_part_doubles(c->halo_nb, p)));
         {
             Scope sc(c, "spmm_shift");
-            HIPCHK(launch_spmm_halo<T>(c->stream, 1, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->halo_rbase, c->rp,
-                                       c->halo_lcol, lb, D, Q, nullptr, 0, lam, act, c->part, c->part_cap, used));
+            HIPCHK(launch_spmm_halo<T>(c->stream, 1, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx,
+                                       c->halo_rbase, c->halo_brp, c->halo_lcol, lb, D, Q, nullptr, 0, lam, act,
+                                       c->part, c->part_cap, used));
         }
         HIPCHK(launch_halo_part_rows(c->stream, c->halo_nb, p, c->part));
         return OFKS_OK;
@@ -1052,6 +1055,7 @@ void free_halo(ofks_ctx *c) {
     dfree(c, c->halo_off);
     dfree(c, c->halo_idx);
     dfree(c, c->halo_rbase);
+    dfree(c, c->halo_brp);
     dfree(c, c->halo_lcol);
     c->halo_nb = 0;
 }
@@ -1089,7 +1093,13 @@ int build_halo_plan(ofks_ctx *c) {
         const int64_t h0 = P.hoff[k], hn = P.hoff[k + 1] - h0;   // 1 <= hn <= HS (the plan check)
         for (int s = 0; s < HS; ++s) hpad[(size_t)k * HS + s] = P.halo[h0 + std::min<int64_t>(s, hn - 1)];
     }
+    // and each block's row pointers at a fixed stride, padded with the next block's first
+    const int BS = halo_row_ptr_stride();
+    std::vector<int64_t> bpad((size_t)nb * BS);
+    for (int64_t k = 0; k < nb; ++k)
+        for (int j = 0; j < BS; ++j) bpad[(size_t)k * BS + j] = rp[std::min(P.row0[k] + j, P.row0[k + 1])];
     CHK(dalloc(c, &c->halo_idx, hpad.size()));
+    CHK(dalloc(c, &c->halo_brp, bpad.size()));
     CHK(dalloc(c, &c->halo_rbase, nb));
     CHK(dalloc(c, &c->halo_lcol, nnz));
     HIPCHK(hipMemcpyAsync(c->halo_row0, P.row0.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
@@ -1098,6 +1108,7 @@ int build_halo_plan(ofks_ctx *c) {
                           c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_lcol, P.lcol.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->halo_rbase, P.rbase.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->halo_brp, bpad.data(), bpad.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->halo_nb = nb;
     return OFKS_OK;
