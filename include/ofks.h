@@ -84,7 +84,7 @@ typedef struct {
     int32_t algorithm;      /* 0: PCAL (Algorithm PCAL: eq. lambda2 multiplier, column B-normalization);
                                1: PLAM (Algorithm PLAM: Lambda = X^T H X (eq. multi), no normalization) */
     int32_t spmm_mode;      /* sparse products: 0 auto (LDS-halo kernel for FP64 blocks with p >= 64 and
-                               FP32 blocks with p >= 256; row-gather otherwise);
+                               FP32 blocks with p >= 96; row-gather otherwise);
                                1 row-gather kernel; 2 LDS-halo kernel (products then fail with OFKS_ESTATE
                                if the matrix has a row with more than 64 entries or more distinct columns
                                than the halo holds).  The kernels agree to rounding. */

@@ -571,8 +571,26 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
                     for (int j = 0; j < VW; ++j) Xs[sl * CP + sg * VW + j] = v[u][j];
                 }
             }
+        } else if (vec) {
+            // ragged last slice of aligned rows: p is a multiple of VW, so a
+            // segment lies wholly inside or wholly past p.  Segments past p
+            // load their row's first segment instead (in bounds, no branch)
+            // and store zeros.
+            const bool in = c < p;
+            const int cc = in ? c : 0;
+            T v[SPT][VW];
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) load_vec<T, VW>(X + (int64_t)hrow[u] * p + cc, v[u]);
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                const int sl = ss + SST * u;
+                if (sl < hn) {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) Xs[sl * CP + sg * VW + j] = in ? v[u][j] : T(0);
+                }
+            }
         } else {
-            // ragged last slice or unaligned rows: element loads, zeros past p
+            // unaligned rows: element loads, zeros past p
 #pragma unroll
             for (int u = 0; u < SPT; ++u) {
                 const int sl = ss + SST * u;

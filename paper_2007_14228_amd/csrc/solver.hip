@@ -515,16 +515,15 @@ size_t partials_needed(ofks_ctx *c, int p) {
 }
 
 // SpMM kernel choice (spmm_mode 0), as measured: the LDS-halo kernel for
-// FP64 blocks that fill its 512-byte slices (p >= 64; faster at p = 64, 128
-// and 512) and for FP32 blocks of two or more slices (p >= 256; at p = 128
-// the two kernels tie, at p = 64 the half-empty slice loses); the row-gather
-// kernel otherwise.  spmm_mode 1 (gather) or 2 (halo) forces one.  Returns
+// FP64 blocks with p >= 64 (faster at p = 64, 96, 128, 160 and 512) and FP32
+// blocks with p >= 96 (faster at p = 96, 128, 160, 192 and 512; at p = 64 the
+// half-empty 128-column slice loses); the row-gather kernel otherwise.  spmm_mode 1 (gather) or 2 (halo) forces one.  Returns
 // 1: halo, 0: gather, -1: halo forced but no plan exists.
 int halo_choice(ofks_ctx *c, int p, size_t elem) {
     const int m = c->prm.spmm_mode;
     if (m == 1) return 0;
     if (m == 2) return c->halo_nb ? 1 : -1;
-    return c->halo_nb && (elem == 8 ? p >= 64 : p >= 256) ? 1 : 0;
+    return c->halo_nb && (elem == 8 ? p >= 64 : p >= 96) ? 1 : 0;
 }
 
 // Y1 = A1 X, Y2 = A2 X (Y2 = NULL: A1 X or A2 X by sel) for the pair matrix w.

@@ -257,18 +257,21 @@ def test_first_iterations_follow_the_oracle_wide_blocks(p, c1):
         assert abs(a["energy"] - b.energy) <= 1e-11 * abs(b.energy)
 
 
-@pytest.mark.parametrize("p", [40, 130, 512])
-def test_fp32_iterations_stay_close_to_the_oracle(p, c1):
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+@pytest.mark.parametrize("p", [40, 130, 260, 512])
+def test_fp32_iterations_stay_close_to_the_oracle(p, mode, c1):
     """The FP32 block path (FP32 matrix-core products) tracks the FP64 oracle
-    over the first iterations to FP32 accuracy."""
+    over the first iterations to FP32 accuracy, through either SpMM kernel
+    (halo: p = 40 and 260 end in a ragged 128-column slice of 16-byte
+    segments, p = 130 takes element loads)."""
     w, d = c1
-    print(f"[gpu] fp32 step c1 p={p}", flush=True)
+    print(f"[gpu] fp32 step c1 p={p} mode={mode}", flush=True)
     prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
     X0 = pcal.chol_gs(prob, wl.random_block(6, d.n, p))
     _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=2, precond="paper"))
     s = _solver_for(w)
     st = _run_gpu(s, X0, 2, beta=w.beta, tol=1e-30, precond="paper", pcg_iters=10, energy_every=1,
-                  precision="f32")
+                  precision="f32", spmm_mode=mode)
     assert st[0]["precision"] == 1
     for a, b in zip(st, hist):
         assert abs(a["kkt"] - b.kkt) <= 1e-4 * b.kkt
