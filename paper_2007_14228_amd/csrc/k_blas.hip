@@ -372,8 +372,16 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int p, int64_t row
 #ifndef OFKS_RG_KC
 #define OFKS_RG_KC 16   // K values staged per LDS round
 #endif
+// Register budget for two waves per SIMD.  Left unconstrained, the compiler
+// takes up to 252 registers (FP64) and 184 (FP32), two waves either way;
+// with this budget the allocation comes to 187 and 128 (four FP32 waves),
+// measured faster at p = 128: FP64 5.33 -> 5.12 ms, FP32 3.08 -> 2.28 ms.
+// A three-wave budget spills in FP64 and is slower (5.59 ms).
+#ifndef OFKS_RG_WPE
+#define OFKS_RG_WPE 2
+#endif
 template <typename T, int NTW, int EPI>
-__global__ __launch_bounds__(256) void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OFKS_RG_WPE))) void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A,
                                                      const T *__restrict__ sa, const T *__restrict__ M,
                                                      T *__restrict__ Y, GradArgs ga) {
     constexpr int TR = 64, TC = 16 * NTW, KC = OFKS_RG_KC;
