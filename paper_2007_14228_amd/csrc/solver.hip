@@ -32,6 +32,18 @@
 #include "dense.hpp"
 #include "halo_plan.hpp"
 
+// Persistent grid of the partial-sum block kernels (k_pcg_r, k_bbdot,
+// k_coldot, the PCG start), a multiple of the 8 XCDs.  At n = 2e6, p = 128
+// (FP64), 1024 blocks beat 2048 and 4096: k_pcg_r 1.26 -> 1.20 ms, k_bbdot
+// 1.46 -> 1.35 ms.  The row-gather shifted SpMM keeps its own grid (at most
+// its resident block count).
+#ifndef OFKS_PART_GRID
+#define OFKS_PART_GRID 1024
+#endif
+#ifndef OFKS_SHIFT_GRID
+#define OFKS_SHIFT_GRID 2048
+#endif
+
 namespace ofks {
 // launchers (k_spmm.hip)
 template <typename T>
@@ -229,7 +241,8 @@ struct ofks_ctx {
     size_t hbuf_cap = 0;
     char *hup = nullptr;     // pinned upload staging, consumed by a cursor reset at each sync
     size_t hup_cap = 0, hup_off = 0;
-    int grid = 2048;         // persistent grid for partial-sum kernels
+    int grid = OFKS_PART_GRID;         // persistent grid for partial-sum kernels
+    int shift_grid = OFKS_SHIFT_GRID;  // grid cap of the row-gather shifted SpMM
     int gemm_rows = 1024;
 
     int k = 0;
@@ -508,7 +521,7 @@ size_t partials_needed(ofks_ctx *c, int p) {
     const size_t gy = (2 * p + tc - 1) / tc;
     size_t need = (size_t)plan.splits * p * 2 * p;
     need = std::max(need, (size_t)c->gemm_rows * gy * (1 + p));
-    need = std::max(need, (size_t)c->grid * std::max(p, 5));
+    need = std::max(need, (size_t)std::max(c->grid, c->shift_grid) * std::max(p, 5));
     need = std::max(need, (size_t)3 * 1024);
     if (c->halo_nb) need = std::max(need, spmm_halo_part_doubles(c->halo_nb, p));   // either precision
     return need;
@@ -557,9 +570,10 @@ int spmm_shift(ofks_ctx *c, int p, const void *lb, const T *lam, const uint8_t *
         HIPCHK(launch_halo_part_rows(c->stream, c->halo_nb, p, c->part));
         return OFKS_OK;
     }
-    CHK(ensure_part(c, (size_t)c->grid * p));
+    CHK(ensure_part(c, (size_t)c->shift_grid * p));
     Scope sc(c, "spmm_shift");
-    HIPCHK(launch_spmm_shift<T>(c->stream, c->grid, c->n, p, c->rp, c->col, lb, lam, act, D, Q, c->part, used));
+    HIPCHK(launch_spmm_shift<T>(c->stream, c->shift_grid, c->n, p, c->rp, c->col, lb, lam, act, D, Q, c->part,
+                                used));
     return OFKS_OK;
 }
 
