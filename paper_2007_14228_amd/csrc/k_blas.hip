@@ -381,9 +381,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int p, int64_t row
 #define OFKS_RG_WPE 2
 #endif
 template <typename T, int NTW, int EPI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OFKS_RG_WPE))) void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A,
-                                                     const T *__restrict__ sa, const T *__restrict__ M,
-                                                     T *__restrict__ Y, GradArgs ga) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OFKS_RG_WPE)))
+void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *__restrict__ sa,
+                    const T *__restrict__ M, T *__restrict__ Y, GradArgs ga) {
     constexpr int TR = 64, TC = 16 * NTW, KC = OFKS_RG_KC;
     using acc_t = typename mfma4<T>::type;
     __shared__ T As[TR][KC + 1];

@@ -530,8 +530,9 @@ size_t partials_needed(ofks_ctx *c, int p) {
 // SpMM kernel choice (spmm_mode 0), as measured: the LDS-halo kernel for
 // FP64 blocks with p >= 64 (faster at p = 64, 96, 128, 160 and 512) and FP32
 // blocks with p >= 96 (faster at p = 96, 128, 160, 192 and 512; at p = 64 the
-// half-empty 128-column slice loses); the row-gather kernel otherwise.  spmm_mode 1 (gather) or 2 (halo) forces one.  Returns
-// 1: halo, 0: gather, -1: halo forced but no plan exists.
+// half-empty 128-column slice loses); the row-gather kernel otherwise.
+// spmm_mode 1 (gather) or 2 (halo) forces one.  Returns 1: halo, 0: gather,
+// -1: halo forced but no plan exists.
 int halo_choice(ofks_ctx *c, int p, size_t elem) {
     const int m = c->prm.spmm_mode;
     if (m == 1) return 0;
@@ -546,7 +547,8 @@ int spmm_pair(ofks_ctx *c, int p, const void *w, const T *X, T *Y1, T *Y2, int s
     if (h < 0) return fail(c, OFKS_ESTATE, "spmm_mode halo: no halo plan for this matrix");
     if (h)
         HIPCHK(launch_spmm_halo<T>(c->stream, 0, c->halo_nb, p, c->halo_row0, c->halo_off, c->halo_idx, c->halo_rbase,
-                                   c->halo_brp, c->halo_lcol, w, X, Y1, Y2, sel, nullptr, nullptr, nullptr, 0, nullptr));
+                                   c->halo_brp, c->halo_lcol, w, X, Y1, Y2, sel, nullptr, nullptr, nullptr, 0,
+                                   nullptr));
     else
         HIPCHK(launch_spmm_pair<T>(c->stream, c->n, p, c->rp, c->col, w, X, Y1, Y2, sel));
     return OFKS_OK;
