@@ -19,6 +19,9 @@ Modules:
   scf     Kohn-Sham H(X), density, Hartree, total energy (Sections 2.1-2.2)
   mlp     learned pointwise preconditioner: forward, backward, Adam (not in the
           paper; the design notes give its definition)
+  gnn     graph learned preconditioner: the pointwise heads plus one damped
+          Jacobi sweep through T over the CSR pattern, and its quadratic-model
+          loss with backpropagation (not in the paper; defined in its header)
 
 Parity status: every function is pinned by a CPU test (tests/test_oracle_*.py)
 except the readings that the paper leaves open (preconditioner inner solve,
