@@ -44,12 +44,12 @@ class Params:
     beta: float = 1.0
     tol: float = 1e-8
     max_iter: int = 1000
-    precond: str = "none"          # "none" | "paper" | "learned"
+    precond: str = "none"          # "none" | "paper" | "learned" | "graph"
     pcg_iters: int = 10
     eta0: float = 0.0              # > 0: fixed first eta
     step_rule: str = "bb2"         # "bb2" | "bb1" | "abb1" | "abb2" | "fixed"
     precond_lambda: str = "lambda2"
-    lp_weights: object = None      # learned form: (W[193], norm[8])
+    lp_weights: object = None      # learned form: (W[193], norm[8]); graph form: (W[226], norm[8])
     fallback_window: int = 5
     fallback_hold: int = 20
     fallback_rule: str = "min"     # fall back when E^k exceeds the "min" or "max" of the window
@@ -147,6 +147,13 @@ def precondition(prob, G, lam_diag, params: Params, kind: str = None):
         W, norm = params.lp_weights
         lhd = prob.diag(prob.Lhval)
         return mlp.apply(W, norm, lhd, prob.diag(prob.Bval), prob.diag(prob.Hval), lam_diag, G)
+    if kind == "graph":
+        # the graph form (oracle/gnn.py), acting alone (no energy fallback)
+        import scipy.sparse as sp
+        from . import gnn
+        W, norm = params.lp_weights
+        mat = lambda v: sp.csr_matrix((v, prob.col, prob.row_ptr), shape=(prob.n, prob.n))
+        return gnn.apply(W, norm, mat(prob.Lhval), mat(prob.Bval), prob.diag(prob.Hval), lam_diag, G)
     if kind != "paper":
         raise ValueError(kind)
     neg = lam_diag < 0

@@ -1,0 +1,44 @@
+"""Opt-in CPU study (several minutes; OFKS_STUDY=1): what the graph form's
+message-passing sweep gains inside PCAL, with the oracle alone.
+
+Held-out graded 24-nucleus problem (seed 2002, n ~ 5e4, p = 16), 300
+iterations from the same start, each preconditioner acting alone.  With the
+heads fixed, the graph form is a Jacobi sweep through T after the pointwise
+Jacobi scaling.  Undamped (ft = 1) its operator is not positive definite on
+these meshes and BB stalls; damped (ft = 1/2) it is far ahead of the
+pointwise form, at one extra sparse product per iteration where the paper's
+inner PCG takes ten."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import fem, gnn, mlp, pcal
+
+pytestmark = pytest.mark.skipif(os.environ.get("OFKS_STUDY") != "1",
+                                reason="oracle-only PCAL study of the graph form: set OFKS_STUDY=1")
+
+
+def test_damped_sweep_beats_the_pointwise_form_inside_pcal():
+    w = wl.make_workload("c3", seed=2002, target_dofs=50_000, p=16)
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(2002, d.n, w.p))
+    norm = np.array([0, 0, 0, 0, 1, 1, 1, 1.0])
+
+    def graph(ft):
+        W = gnn.init_weights(0)
+        W[-2:] = [0.0, ft]
+        return ("graph", (W, norm))
+
+    cases = {"none": ("none", None), "pointwise": ("learned", (mlp.init_weights(0), norm)), "graph ft=1": graph(1.0),
+             "graph ft=1/2": graph(0.5), "paper m=10": ("paper", None)}
+    rel = {}
+    for name, (kind, lw) in cases.items():
+        _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=300, precond=kind,
+                                                  lp_weights=lw, fallback_window=0))
+        rel[name] = hist[-1].rel
+        print(f"[study] n={d.n} p={w.p} {name}: rel after 300 iterations {rel[name]:.3e}", flush=True)
+    assert rel["graph ft=1/2"] < 1e-2 * rel["pointwise"]
+    assert rel["graph ft=1"] > rel["pointwise"]
