@@ -34,6 +34,9 @@ def test_damped_sweep_beats_the_pointwise_form_inside_pcal():
 
     cases = {"none": ("none", None), "pointwise": ("learned", (mlp.init_weights(0), norm)), "graph ft=1": graph(1.0),
              "graph ft=1/2": graph(0.5), "paper m=10": ("paper", None)}
+    # OFKS_STUDY_FT="0.3,0.7": further fixed damping values, reported only
+    for v in filter(None, os.environ.get("OFKS_STUDY_FT", "").split(",")):
+        cases[f"graph ft={float(v):g}"] = graph(float(v))
     rel = {}
     for name, (kind, lw) in cases.items():
         _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=300, precond=kind,
