@@ -150,7 +150,10 @@ def traffic_from_profiles(kernel, workload):
         return None
     src = os.path.join(ROOT, "paper_2007_14228_amd", "csrc", rec.get("source", "k_spmm.hip"))
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return rec.get("bytes_per_launch") if h == rec.get("source_sha") else None
+    if h != rec.get("source_sha"):
+        return None
+    return dict(bytes=rec.get("bytes_per_launch"), commit=rec.get("commit"), command=rec.get("command"),
+                fetch_scale=rec.get("fetch_scale"), write_scale=rec.get("write_scale"))
 
 
 def run_to_tol(torch, s, X0, tol, params, weights=None):
@@ -177,11 +180,23 @@ def run_to_tol(torch, s, X0, tol, params, weights=None):
                 fp32_iterations=int(sum(1 for x in stats[:-1] if x["precision"] == 1)))
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, X0_host, pcg_iters, iters=2):
-    """The oracle as it stands, the first `iters` PCAL iterations (paper
-    preconditioner) on the full workload; reported as iterations per second.
-    From a random start every Lambda_ll is positive at k = 0, so the first
-    iteration takes the identity branch (no inner solve) and is the cheap one."""
+    """The oracle as it stands, timed over `iters` PCAL iterations with the
+    paper preconditioner on the full workload, reported as iterations per
+    second.  From a random start every Lambda_ll is positive at k = 0, so
+    iteration 0 takes the identity branch (no inner solve); the clock
+    therefore runs from the evaluation of X^1 to that of X^(1+iters), i.e.
+    over steady-state iterations that include the inner solves."""
     from oracle import fem, pcal, scf
     log("cpu baseline: oracle discretization")
     t = time.perf_counter()
@@ -192,17 +207,24 @@ def cpu_baseline(w, X0_host, pcg_iters, iters=2):
     else:
         prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
     X0 = pcal.chol_gs(prob, X0_host)
-    log(f"cpu baseline: setup {setup:.1f}s; timing one iteration")
+    log(f"cpu baseline: setup {setup:.1f}s; timing iterations 1..{iters}")
+    stamps = {}
+
+    def at_iterate(k, *_):                      # called once X^k is evaluated (HX, BX, Gram)
+        stamps[k] = time.perf_counter()
+
     t = time.perf_counter()
-    pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=iters, precond="paper",
-                                    pcg_iters=pcg_iters))
-    dt = time.perf_counter() - t
-    # pcal(max_iter=k) evaluates X^0..X^k and takes k steps
+    pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=1 + iters, precond="paper",
+                                    pcg_iters=pcg_iters), callback=at_iterate)
+    total = time.perf_counter() - t
+    dt = stamps[1 + iters] - stamps[1]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=iters / dt, unit="iter/s", cores=threads, kind="oracle",
-                sample=f"the first {iters} PCAL iterations (and the evaluation of the last iterate) of the same "
-                       f"workload from the same start, FP64, paper preconditioner m={pcg_iters} (iteration 0 takes "
-                       f"the identity branch): {dt:.2f} s; oracle setup {setup:.1f} s not included")
+                cpu=cpu_model(), host_cpus=os.cpu_count(),
+                sample=f"PCAL iterations 1..{iters} (each with the m={pcg_iters} inner solves of the paper "
+                       f"preconditioner) of the same workload from the same start, FP64, timed from the "
+                       f"evaluation of X^1 to that of X^{1 + iters}: {dt:.2f} s; iteration 0 (identity branch) and "
+                       f"the oracle setup ({setup:.1f} s) are not included; {total:.1f} s in all")
 
 
 def main():
@@ -265,9 +287,17 @@ def main():
         alg = algorithmic_bytes_spmm_dual(n, nnz, p, wbytes)
         kern = "k_spmm_pair"
     achieved = alg / (avg * 1e-3) / 1e9
+    # traffic: HBM bytes per launch from the committed rocprofv3 counter runs
+    # (not measured in this run), reported only while the kernel source still
+    # has the hash it was measured at
+    tr = traffic_from_profiles(kern, a.workload)
     roofline = dict(bound="hbm", kernel=kern, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kern, a.workload),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=tr["bytes"] if tr else None,
                     avg_launch_ms=round(avg, 4), algorithmic_bytes_per_launch=int(alg))
+    if tr:
+        roofline["traffic_source"] = (f"profiles/traffic.json: rocprofv3 FETCH_SIZE x{tr['fetch_scale']} + "
+                                      f"WRITE_SIZE x{tr['write_scale']} (copy-calibrated), measured at commit "
+                                      f"{tr['commit']}, not in this run")
 
     out = {
         "metric": METRIC,

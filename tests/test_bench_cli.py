@@ -35,7 +35,7 @@ def _fake_root(tmp_path, source_text, recorded_text):
 def test_traffic_is_reported_for_the_measured_source(tmp_path, monkeypatch):
     _fake_root(tmp_path, "kernel v1\n", "kernel v1\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.traffic_from_profiles("k_spmm_shift", "c3") == 5781812918
+    assert bench.traffic_from_profiles("k_spmm_shift", "c3")["bytes"] == 5781812918
 
 
 def test_traffic_is_null_once_the_source_changes(tmp_path, monkeypatch):

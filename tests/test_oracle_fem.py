@@ -143,3 +143,23 @@ def test_nuclear_repulsion_closed_form():
     R = np.array([[0.0, 0, 0], [2.0, 0, 0], [0, 0, 4.0]])
     assert math.isclose(fem.nuclear_repulsion(Z, R), 8 / 2 + 6 / 4 + 48 / math.sqrt(20.0),
                         rel_tol=1e-15)
+
+
+def test_local_rows_equal_the_full_assembly(graded):
+    """fem.local_rows (the assembly of single rows from the tetrahedra around
+    them, used for sampled checks at sizes the full assembly cannot reach)
+    gives the same columns and values as discretize.  Every 7th row is
+    compared, which includes rows next to the boundary and rows at the
+    refined nuclei.  Planted mistakes this catches (checked): a tetrahedron
+    dropped from the local set, the potential term's weights |K|/4 changed."""
+    mesh, Z, R = graded
+    d = fem.discretize(mesh, Z, R)
+    rows = np.arange(0, d.n, 7)
+    loc = fem.local_rows(mesh, Z, R, rows)
+    assert sorted(loc) == list(rows)
+    for i in rows:
+        s, e = d.row_ptr[i], d.row_ptr[i + 1]
+        cols, Lv, Bv, Mv = loc[int(i)]
+        assert np.array_equal(cols, d.col[s:e])
+        for got, ref in ((Lv, d.L[s:e]), (Bv, d.B[s:e]), (Mv, d.Mext[s:e])):
+            assert np.allclose(got, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())

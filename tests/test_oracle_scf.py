@@ -97,3 +97,30 @@ def test_hydrogen_ground_state_approaches_minus_one_half():
         vals.append(lam)
     assert -0.5 < vals[1] < vals[0] < -0.3
     assert vals[1] < -0.44
+
+
+def test_hartree_potential_of_a_known_density():
+    """The Hartree potential solves -Laplace V_H = 4 pi rho (Section 2.1's
+    Hartree term in atomic units) with zero boundary values (the reading of
+    the unstated boundary condition).  For rho = 3 pi / (4 a^2) prod_d
+    cos(pi x_d / a) on [-a/2, a/2]^3 the exact potential is prod_d cos(pi x_d
+    / a) and the Hartree energy (1/2) int V_H rho = 3 pi a / 64.  The oracle's
+    nodal potential and U.b/2 converge to both at O(h^2).  Planted mistake
+    this catches (checked): 2 pi in place of 4 pi in L U = 4 pi b."""
+    a = 6.0
+    errs, eerr = [], []
+    for cells in (8, 16):
+        ax = wl.uniform_axis(-a / 2, a / 2, cells)
+        mesh = wl.kuhn_mesh(ax, ax, ax)
+        d = fem.discretize(mesh, np.zeros(0), np.zeros((0, 3)))
+        prob = scf.KSProblem(d, np.zeros(0), np.zeros((0, 3)))
+        xq = fem.quad_points(mesh.xyz, mesh.tets.astype(np.int64))
+        rho_q = 3 * np.pi / (4 * a * a) * np.prod(np.cos(np.pi * xq / a), axis=-1)
+        b = prob.load_vector(rho_q)
+        U = prob.hartree(b)
+        exact = np.prod(np.cos(np.pi * mesh.xyz[mesh.dirichlet == 0] / a), axis=-1)
+        errs.append(np.abs(U - exact).max())
+        eerr.append(abs(0.5 * float(U @ b) - 3 * np.pi * a / 64) / (3 * np.pi * a / 64))
+    assert errs[1] < 0.03 and eerr[1] < 0.03
+    assert 3.0 < errs[0] / errs[1] < 5.0
+    assert 3.0 < eerr[0] / eerr[1] < 5.0
