@@ -187,6 +187,19 @@ int ofks_get_density(ofks_ctx *ctx, double *dev_rho);
 /* HX = H X and BX = B X (dual SpMM) on the current system; device f64 blocks n x p. */
 int ofks_spmm(ofks_ctx *ctx, int32_t p, const double *X, double *HX, double *BX);
 
+/* One sparse product in either block precision, through the kernel the
+ * iteration would use (params.spmm_mode):
+ *   op 0: Y1 = H X, Y2 = B X (the dual product of eq. PCAL-main's gradient);
+ *   op 1: Y1_l = (L/2 - lam_l B) X_l for columns with lam_l < 0 and 0 for the
+ *         others (the operator T_l of eq. precondition-T); Y2 unused (may be
+ *         NULL); lam host f64[p].
+ * precision OFKS_F64: X, Y1, Y2 device f64[n*p]; OFKS_F32: device f32[n*p],
+ * with the FP32 copies of the matrix values (made on first use).  Blocks are
+ * row-major and caller-owned; Y1 and Y2 must not overlap X.  EINVAL on bad
+ * arguments; ESTATE without a system (op 1: without L/2). */
+int ofks_spmm_ex(ofks_ctx *ctx, int32_t p, int32_t precision, int32_t op, const double *lam, const void *X,
+                 void *Y1, void *Y2);
+
 /* S = X^T BX and L0 = X^T HX (tall-skinny Gram), host f64[p*p] each, not symmetrized. */
 int ofks_gram(ofks_ctx *ctx, int32_t p, const double *X, const double *HX, const double *BX,
               double *S, double *L0);

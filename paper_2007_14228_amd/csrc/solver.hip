@@ -1159,6 +1159,25 @@ void free_system(ofks_ctx *c) {
     c->has_lhalf = false;
 }
 
+template <typename T>
+int spmm_ex_typed(ofks_ctx *c, int p, int op, const double *lam, const T *X, T *Y1, T *Y2) {
+    if (op == 0) return spmm_pair<T>(c, p, hbT<T>(c), X, Y1, Y2, 0);
+    T *lamd = nullptr;
+    uint8_t *act = nullptr;
+    CHK(dalloc(c, &lamd, p));
+    CHK(dalloc(c, &act, p));
+    std::vector<double> lv(lam, lam + p);
+    std::vector<uint8_t> ah(p);
+    for (int i = 0; i < p; ++i) ah[i] = lam[i] < 0.0 ? 1 : 0;
+    int rc = upload<T>(c, lamd, lv);
+    if (rc >= 0) rc = upload_bytes(c, act, ah.data(), p);
+    int used = 0;
+    if (rc >= 0) rc = spmm_shift<T>(c, p, lbT<T>(c), lamd, act, X, Y1, &used);
+    const int rs = sync(c);
+    dfree(c, lamd);
+    dfree(c, act);
+    return rc < 0 ? rc : rs;
+}
 }  // namespace
 
 // ===========================================================================
@@ -1714,6 +1733,27 @@ int ofks_spmm(ofks_ctx *c, int32_t p, const double *X, double *HX, double *BX) {
     if (!c->has_system) return fail(c, OFKS_ESTATE, "spmm: no system");
     if (p <= 0 || p > 1024 || !X || !HX || !BX) return fail(c, OFKS_EINVAL, "spmm: bad arguments");
     CHK(spmm_pair<double>(c, p, c->hb, X, HX, BX, 0));
+    return sync(c);
+}
+
+
+int ofks_spmm_ex(ofks_ctx *c, int32_t p, int32_t precision, int32_t op, const double *lam, const void *X, void *Y1,
+                 void *Y2) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "spmm_ex: no system");
+    if (p <= 0 || p > 1024 || !X || !Y1) return fail(c, OFKS_EINVAL, "spmm_ex: bad arguments");
+    if (op != 0 && op != 1) return fail(c, OFKS_EINVAL, "spmm_ex: op must be 0 (dual) or 1 (shifted)");
+    if (op == 0 && !Y2) return fail(c, OFKS_EINVAL, "spmm_ex: the dual product needs Y2");
+    if (op == 1 && (!lam || !c->has_lhalf)) return fail(c, OFKS_ESTATE, "spmm_ex: the shifted product needs L/2 and lam");
+    if (precision != OFKS_F64 && precision != OFKS_F32) return fail(c, OFKS_EINVAL, "spmm_ex: bad precision");
+    if (op == 1) CHK(ensure_part(c, std::max((size_t)c->shift_grid * p,
+                                             c->halo_nb ? spmm_halo_part_doubles(c->halo_nb, p) : (size_t)0)));
+    if (precision == OFKS_F64) {
+        CHK(spmm_ex_typed<double>(c, p, op, lam, (const double *)X, (double *)Y1, (double *)Y2));
+    } else {
+        if (!c->hb32) CHK(ensure_f32_matrices(c));
+        CHK(spmm_ex_typed<float>(c, p, op, lam, (const float *)X, (float *)Y1, (float *)Y2));
+    }
     return sync(c);
 }
 

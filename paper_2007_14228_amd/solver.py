@@ -225,6 +225,32 @@ class Solver:
         self._check(self.lib.ofks_spmm(self.h, int(X.shape[1]), _dev_ptr(X), _dev_ptr(HX), _dev_ptr(BX)))
         return HX, BX
 
+    def spmm_ex(self, X, op: str = "dual", lam: Optional[np.ndarray] = None):
+        """op "dual": (H X, B X); op "shift": (L/2 - lam_l B) X_l on columns
+        with lam_l < 0 (zero elsewhere).  The precision follows X's dtype
+        (float64 or float32)."""
+        import torch
+        _check_block(X, self.n)
+        prec = {torch.float64: 0, torch.float32: 1}.get(X.dtype)
+        if prec is None:
+            raise TypeError("X must be float64 or float32")
+        name = "float64" if prec == 0 else "float32"
+        p = int(X.shape[1])
+        Y1 = torch.empty_like(X)
+        if op == "dual":
+            Y2 = torch.empty_like(X)
+            self._check(self.lib.ofks_spmm_ex(self.h, p, prec, 0, None, _dev_ptr(X, name), _dev_ptr(Y1, name),
+                                              _dev_ptr(Y2, name)))
+            return Y1, Y2
+        if op != "shift":
+            raise ValueError(op)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (p,):
+            raise ValueError("lam must have one entry per column")
+        self._check(self.lib.ofks_spmm_ex(self.h, p, prec, 1, _np_ptr(lam), _dev_ptr(X, name),
+                                          _dev_ptr(Y1, name), None))
+        return Y1
+
     def gram(self, X, HX, BX):
         for Y in (X, HX, BX):
             _check_block(Y, self.n)

@@ -266,6 +266,16 @@ def random_block(seed: int, n: int, p: int) -> np.ndarray:
     return rng.standard_normal((n, p))
 
 
+def device_random_block(seed: int, n: int, p: int, device: str = "cuda"):
+    """i.i.d. N(0,1) block (n x p, row-major, float64) drawn on the device by
+    torch's seeded generator, for blocks too large to draw and upload from the
+    host; the rows an oracle check needs are copied back from it."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn((n, p), dtype=torch.float64, device=device, generator=g)
+
+
 def random_block_chunks(seed: int, n: int, p: int, chunk_rows: int = 1 << 18):
     """The rows of random_block(seed, n, p) in consecutive chunks (r0, r1, rows),
     for blocks too large to hold at once; the same numbers as one call."""
