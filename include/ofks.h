@@ -204,6 +204,21 @@ int ofks_spmm_ex(ofks_ctx *ctx, int32_t p, int32_t precision, int32_t op, const 
 int ofks_gram(ofks_ctx *ctx, int32_t p, const double *X, const double *HX, const double *BX,
               double *S, double *L0);
 
+/* ofks_gram for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same S = X^T BX and L0 = X^T HX (host f64[p*p] each, not symmetrized,
+ * equal to ofks_gram's up to the summation order), with the split-K partial
+ * tiles and their sums in a fixed 64 MiB device array that the library holds
+ * per device until the process ends.  It calls no hipMalloc, hipFree or
+ * hipHostMalloc; with large p it uses fewer row splits than ofks_gram.
+ * 1 <= p <= OFKS_GRAM_NOALLOC_MAX_P, else OFKS_ECAPACITY.  Every call on one
+ * device shares that array: calls that overlap on one device (two contexts
+ * on different streams, or two threads) race and must be serialized by the
+ * caller.  Synchronizes the context's stream. */
+#define OFKS_GRAM_NOALLOC_MAX_P 1024
+int ofks_gram_noalloc(ofks_ctx *ctx, int32_t p, const double *X, const double *HX, const double *BX,
+                      double *S, double *L0);
+
 /* P = T^{-1} G columnwise by the fixed-iteration Jacobi-PCG of the paper
  * preconditioner; lam host f64[p]; columns with lam >= 0 are copied. */
 int ofks_precondition(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, double *P);

@@ -85,6 +85,7 @@ SIGNATURES = [
     ("ofks_spmm", I32, [P, I32, P, P, P]),
     ("ofks_spmm_ex", I32, [P, I32, I32, I32, P, P, P, P]),
     ("ofks_gram", I32, [P, I32, P, P, P, P, P]),
+    ("ofks_gram_noalloc", I32, [P, I32, P, P, P, P, P]),
     ("ofks_precondition", I32, [P, I32, P, P, P]),
     ("ofks_build_hamiltonian", I32, [P, I32, P, P, P, P, P, P]),
     ("ofks_lp_set_weights", I32, [P, P, P]),

@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,14 @@
 #ifndef OFKS_SHIFT_GRID
 #define OFKS_SHIFT_GRID 2048
 #endif
+
+// Scratch of the allocation-free Gram entry point (ofks_gram_noalloc): the
+// split-K partial tiles and, after them, their column sum.  One copy per
+// device, alive until the process ends.  Host code never passes the array's
+// name to a kernel or a copy: it holds the device address that
+// hipGetSymbolAddress returns for each device (noalloc_scratch below).
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(8) << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
 
 namespace ofks {
 // launchers (k_spmm.hip)
@@ -266,6 +275,8 @@ struct ofks_ctx {
     int lp_objective = 0;        // 0: Euclidean imitation of T^-1 g, 1: energy-norm imitation
     void *lp_u = nullptr;        // T (J G) for the energy-norm samples
     size_t lp_u_bytes = 0;
+
+    double *scratch_dev = nullptr;   // this device's copy of `scratch` (ofks_gram_noalloc)
 
     // timing
     bool timing = false;
@@ -1178,6 +1189,22 @@ int spmm_ex_typed(ofks_ctx *c, int p, int op, const double *lam, const T *X, T *
     dfree(c, act);
     return rc < 0 ? rc : rs;
 }
+// Device address of `scratch` on the current device, resolved once per
+// device (each device holds its own copy at its own address).
+int noalloc_scratch(int device, double **out) {
+    static std::mutex mu;
+    static std::map<int, double *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return OFKS_EHIP;
+        it = addr.emplace(device, (double *)ptr).first;
+    }
+    *out = it->second;
+    return OFKS_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1214,7 +1241,7 @@ int ofks_create(ofks_ctx **out, void *hip_stream) {
     if (!out) return OFKS_EINVAL;
     ofks_ctx *c = new ofks_ctx();
     c->stream = (hipStream_t)hip_stream;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess || noalloc_scratch(c->device, &c->scratch_dev) != OFKS_OK) {
         delete c;
         return OFKS_EHIP;
     }
@@ -1769,6 +1796,35 @@ int ofks_gram(ofks_ctx *c, int32_t p, const double *X, const double *HX, const d
     CHK(rc);
     std::memcpy(S, St.data(), sizeof(double) * p * p);
     std::memcpy(L0, Lt.data(), sizeof(double) * p * p);
+    return OFKS_OK;
+}
+
+int ofks_gram_noalloc(ofks_ctx *c, int32_t p, const double *X, const double *HX, const double *BX, double *S,
+                      double *L0) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "gram_noalloc: no system");
+    if (!X || !HX || !BX || !S || !L0) return fail(c, OFKS_EINVAL, "gram_noalloc: null pointer");
+    if (p <= 0 || p > OFKS_GRAM_NOALLOC_MAX_P)
+        return fail(c, OFKS_ECAPACITY, "gram_noalloc: p = %d outside 1..%d (the fixed scratch of %zu bytes)", p,
+                    OFKS_GRAM_NOALLOC_MAX_P, NOALLOC_SCRATCH_DOUBLES * sizeof(double));
+    if (!c->scratch_dev) return fail(c, OFKS_ESTATE, "gram_noalloc: no scratch address for this device");
+    // the split-K plan of ofks_gram, with fewer row splits where its partial
+    // tiles would not fit beside their column sum
+    const size_t pp2 = (size_t)p * 2 * p;
+    const int64_t max_splits = (int64_t)(NOALLOC_SCRATCH_DOUBLES / pp2) - 1;
+    GramPlan plan = gram_plan(c->n, p, 2048);
+    if (plan.splits > max_splits) plan = gram_plan(c->n, p, (int)(max_splits * plan.gx * plan.gy));
+    if (plan.splits < 1 || plan.splits > max_splits)
+        return fail(c, OFKS_EINTERNAL, "gram_noalloc: no split plan fits the scratch");
+    double *part = c->scratch_dev;
+    double *red = c->scratch_dev + (size_t)plan.splits * pp2;
+    HIPCHK(launch_gram<double>(c->stream, c->n, p, plan, X, BX, HX, part, (size_t)plan.splits * pp2));
+    HIPCHK(launch_colsum(c->stream, plan.splits, (int64_t)pp2, part, red));
+    // rows of the sums hold [S row | L0 row]; split them straight into the caller's arrays
+    const size_t rowb = (size_t)p * sizeof(double);
+    HIPCHK(hipMemcpy2DAsync(S, rowb, red, 2 * rowb, rowb, p, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpy2DAsync(L0, rowb, red + p, 2 * rowb, rowb, p, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return OFKS_OK;
 }
 
