@@ -51,8 +51,8 @@ enum {
     OFKS_EINTERNAL = -8       /* a host-side consistency check of the library's own data failed */
 };
 
-/* Preconditioner choice (eq. precondition-T and the learned form). */
-enum { OFKS_PRECOND_NONE = 0, OFKS_PRECOND_PAPER = 1, OFKS_PRECOND_LEARNED = 2 };
+/* Preconditioner choice (eq. precondition-T, the learned pointwise form and the learned graph form). */
+enum { OFKS_PRECOND_NONE = 0, OFKS_PRECOND_PAPER = 1, OFKS_PRECOND_LEARNED = 2, OFKS_PRECOND_GRAPH = 3 };
 /* Step-size rule, Section 4.4 (Barzilai-Borwein variants). */
 enum { OFKS_STEP_BB2 = 0, OFKS_STEP_BB1 = 1, OFKS_STEP_ABB1 = 2, OFKS_STEP_ABB2 = 3,
        OFKS_STEP_FIXED = 4 };
@@ -88,7 +88,8 @@ typedef struct {
                                1 row-gather kernel; 2 LDS-halo kernel (products then fail with OFKS_ESTATE
                                if the matrix has a row with more than 64 entries or more distinct columns
                                than the halo holds).  The kernels agree to rounding. */
-    int32_t reserved[1];
+    int32_t fallback_stall; /* learned forms: also fall back when the fallback_stall iterates before the
+                               current one did not halve the lowest rel (<= 0: never; default 30) */
 } ofks_params;
 
 typedef struct {
@@ -238,7 +239,9 @@ int ofks_build_hamiltonian(ofks_ctx *ctx, int32_t p, const double *X, double *rh
  *   J_il = 1/(L_ii/2 - Lambda_ll B_ii) if Lambda_ll < 0, else 1
  * and falls back to the paper preconditioner (eq. precondition-T) for
  * fallback_hold iterations whenever the energy of an iterate exceeds the
- * minimum of the previous fallback_window iterates.  Weight vector (193
+ * minimum (fallback_rule 1: maximum) of the previous fallback_window
+ * iterates, or the fallback_stall iterates before it did not halve the
+ * lowest residual (a stall while the energy falls).  Weight vector (193
  * floats): [W1 (32 x 4 row-major), b1 (32), W2 (32), b2 (1)]; norm (8 floats):
  * feature means then standard deviations (all > 0). */
 int ofks_lp_set_weights(ofks_ctx *ctx, const float *host_w, const float *host_norm);
@@ -277,6 +280,58 @@ int ofks_lp_loss_grad(ofks_ctx *ctx, const float *dev_samples, int64_t m, const 
  * f64[p]), using the context's weights (parity checks). */
 int ofks_lp_apply(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, double *P);
 
+/* Raw features [n, p, 4] (device f32, row-major) of the learned forms for a
+ * device block G (f64 n x p): log(L_ii/2), log B_ii, (H_ii - L_ii/2)/B_ii,
+ * g_il / rms(g_l) (0 where the column is zero). */
+int ofks_lp_features(ofks_ctx *ctx, int32_t p, const double *G, float *dev_feat);
+
+/* ---- learned graph preconditioner (not in the paper) -------------------------
+ *
+ * With params.precond = OFKS_PRECOND_GRAPH the step uses one damped Jacobi
+ * sweep through the paper's operator T_l (eq. precondition-T) over the CSR
+ * pattern, with a per-(row, column) scale and smoothing weight from a
+ * pointwise network on the learned forms' features:
+ *   (fs, ft) = W2 tanh(W1 x + b1) + b2,  Z = exp(fs) J G,
+ *   P = Z + ft J (G - T Z)       (T = I and J = 1 on columns with Lambda_ll >= 0),
+ * and falls back to the paper preconditioner like the pointwise form.
+ * Weights (226 floats): [W1 (32 x 4 row-major), b1 (32), W2 (2 x 32 row-major,
+ * row 0 for fs), b2 (2)]; norm (8 floats): feature means, then standard
+ * deviations (> 0).  Network arithmetic is FP32. */
+int ofks_gl_set_weights(ofks_ctx *ctx, const float *host_w, const float *host_norm);
+
+/* P for a device block G (f64 n x p, P must not alias G) and host shifts
+ * lam[p], with the context's weights (parity checks). */
+int ofks_gl_apply(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, double *P);
+
+/* The training objective for one block and its gradient (host f64 scalar and
+ * f64[226]) at the context's weights:
+ *   loss = sum_l w_l (P_l^T T_l P_l / 2 - G_l^T P_l),  w_l = 1 / (G_l^T J_l G_l),
+ * the quadratic model of each column's system, smallest where P_l = T_l^-1 G_l. */
+int ofks_gl_loss_grad(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, double *loss, double *grad);
+
+/* Training snapshots: while dev_buf != NULL, every `every`-th FP64 iterate that
+ * applies the paper preconditioner writes its gradient block G (n x p) into
+ * the next slot of dev_buf (caller-owned, max_blocks * n * p doubles) and
+ * keeps its shifts; a new buffer restarts the count, NULL stops capturing. */
+int ofks_gl_capture(ofks_ctx *ctx, double *dev_buf, int32_t max_blocks, int64_t every);
+/* Count of captured blocks and their shifts (host f64[count * p] or NULL). */
+int ofks_gl_captured(ofks_ctx *ctx, int32_t *count, double *host_lam);
+
+/* Adam on the training objective over `count` device blocks G (f64, count
+ * x n x p, on the context's system) with host shifts lam (count x p), for
+ * `epochs` passes, one step per block.  w_inout (host f32[226]) holds the
+ * starting weights and receives the result (also set on the context);
+ * adam_inout (host f32[453]: first moments, second moments, step count)
+ * carries the optimizer state across calls and systems; loss_out (host
+ * f64[epochs * count] or NULL) receives each block's loss before its step.
+ * The standardization must have been set with ofks_gl_set_weights. */
+int ofks_gl_train(ofks_ctx *ctx, int32_t p, const double *dev_G, const double *host_lam, int32_t count,
+                  int32_t epochs, float lr, float *w_inout, float *adam_inout, double *loss_out);
+
+/* Standardization of the node features over the current system's rows (host
+ * f32[8]: means, then standard deviations; the residual feature gets 0 and 1). */
+int ofks_gl_feature_norm(ofks_ctx *ctx, float *host_norm);
+
 /* ---- timing ------------------------------------------------------------ */
 
 /* Kernel timers (HIP events on the context stream).  enable = 1 starts
@@ -284,7 +339,8 @@ int ofks_lp_apply(ofks_ctx *ctx, int32_t p, const double *lam, const double *G, 
 int ofks_timing(ofks_ctx *ctx, int32_t enable);
 /* Totals for a kernel class: name is one of "spmm_dual", "spmm_shift",
  * "gram", "update_a", "update_b", "pcg_r", "pcg_dx", "density", "poisson",
- * "assemble_h", "bbdot", "mlp", "mlp_train".  ms = summed duration, launches = count. */
+ * "assemble_h", "bbdot", "mlp", "mlp_train", "graph", "graph_train".  ms = summed duration,
+ * launches = count. */
 int ofks_timer_get(ofks_ctx *ctx, const char *name, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

@@ -26,6 +26,10 @@ Readings where the paper is silent (each also listed in the design notes):
   * eta_0 = ||P^0||_F / ||X^0||_F unless given; BB values are clamped to
     [1e-8, 1e8] * eta_0 and a zero or non-finite <S, Y> keeps the last eta;
   * the multiplier in kkt is Lambda0 = X^T H X.
+Learned forms (not in the paper): the network's output replaces the paper
+preconditioner, which takes over for fallback_hold iterations when the energy
+rises above the window's minimum (or maximum) or when the fallback_stall
+iterates before the current one did not halve the lowest residual.
 """
 from __future__ import annotations
 
@@ -53,6 +57,7 @@ class Params:
     fallback_window: int = 5
     fallback_hold: int = 20
     fallback_rule: str = "min"     # fall back when E^k exceeds the "min" or "max" of the window
+    fallback_stall: int = 30       # ... or when the last fallback_stall iterates did not halve the lowest rel (<= 0: off)
     algorithm: str = "pcal"        # "pcal" (Algorithm PCAL) | "plam" (Algorithm PLAM)
 
 
@@ -148,7 +153,7 @@ def precondition(prob, G, lam_diag, params: Params, kind: str = None):
         lhd = prob.diag(prob.Lhval)
         return mlp.apply(W, norm, lhd, prob.diag(prob.Bval), prob.diag(prob.Hval), lam_diag, G)
     if kind == "graph":
-        # the graph form (oracle/gnn.py), acting alone (no energy fallback)
+        # the graph form (oracle/gnn.py)
         import scipy.sparse as sp
         from . import gnn
         W, norm = params.lp_weights
@@ -219,10 +224,12 @@ def pcal(prob, X0: np.ndarray, params: Params,
         G = HX + BX @ (params.beta * (S - I) - Lam)
         lam_diag = np.diag(Lam) if params.precond_lambda == "lambda2" else np.diag(L0)
         kind = params.precond
-        if params.precond == "learned":
+        if params.precond in ("learned", "graph"):
             # fall back to the paper preconditioner for fallback_hold steps when
-            # E^k exceeds the minimum (or maximum) of the previous fallback_window
-            # energies; fallback_window <= 0: never
+            # E^k exceeds the minimum (or maximum) of the previous
+            # fallback_window energies (fallback_window <= 0: never), or when the
+            # fallback_stall iterates before this one did not halve the lowest
+            # residual (a stall while the energy still falls; <= 0: never)
             use_learned = hold == 0
             if params.fallback_window > 0:
                 ref = (max if params.fallback_rule == "max" else min)(ehist) if ehist else None
@@ -230,7 +237,12 @@ def pcal(prob, X0: np.ndarray, params: Params,
                     hold = max(1, params.fallback_hold)
                     use_learned = False
                 ehist = (ehist + [E])[-params.fallback_window:]
-            kind = "learned" if use_learned else "paper"
+            if use_learned and params.fallback_stall > 0 and k > params.fallback_stall:
+                prev = [h.rel for h in hist[:-1]]       # rel of X^0 .. X^(k-1)
+                if min(prev) > 0.5 * min(prev[:k - params.fallback_stall]):
+                    hold = max(1, params.fallback_hold)
+                    use_learned = False
+            kind = params.precond if use_learned else "paper"
             if hold > 0 and not use_learned:
                 hold -= 1
         P = precondition(prob, G, lam_diag.copy(), params, kind)

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libofks.so")
 
 OFKS_OK = 0
 OFKS_NOT_CONVERGED = 1
-PRECOND = {"none": 0, "paper": 1, "learned": 2}
+PRECOND = {"none": 0, "paper": 1, "learned": 2, "graph": 3}
 STEP = {"bb2": 0, "bb1": 1, "abb1": 2, "abb2": 3, "fixed": 4}
 PRECISION = {"f64": 0, "f32": 1}
 
@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("use_graphs", _c_int32),
         ("algorithm", _c_int32),
         ("spmm_mode", _c_int32),
-        ("reserved", _c_int32 * 1),
+        ("fallback_stall", _c_int32),
     ]
 
 
@@ -94,6 +94,14 @@ SIGNATURES = [
     ("ofks_lp_train", I32, [P, P, I64, I32, ctypes.c_float, P, P, P]),
     ("ofks_lp_loss_grad", I32, [P, P, I64, P, P, ctypes.POINTER(_c_double), P]),
     ("ofks_lp_apply", I32, [P, I32, P, P, P]),
+    ("ofks_lp_features", I32, [P, I32, P, P]),
+    ("ofks_gl_set_weights", I32, [P, P, P]),
+    ("ofks_gl_apply", I32, [P, I32, P, P, P]),
+    ("ofks_gl_loss_grad", I32, [P, I32, P, P, ctypes.POINTER(_c_double), P]),
+    ("ofks_gl_capture", I32, [P, P, I32, I64]),
+    ("ofks_gl_captured", I32, [P, ctypes.POINTER(I32), P]),
+    ("ofks_gl_train", I32, [P, I32, P, P, I32, I32, ctypes.c_float, P, P, P]),
+    ("ofks_gl_feature_norm", I32, [P, P]),
     ("ofks_timing", I32, [P, I32]),
     ("ofks_timer_get", I32, [P, ctypes.c_char_p, ctypes.POINTER(_c_double), ctypes.POINTER(I64)]),
 ]

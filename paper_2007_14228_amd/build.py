@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libofks.so")
-SOURCES = ["k_spmm.hip", "k_blas.hip", "k_mesh.hip", "k_density.hip", "k_mlp.hip", "solver.hip"]
+SOURCES = ["k_spmm.hip", "k_blas.hip", "k_mesh.hip", "k_density.hip", "k_mlp.hip", "k_gnn.hip", "solver.hip"]
 ARCH = os.environ.get("OFKS_ARCH", "gfx950")
 
 

@@ -170,6 +170,28 @@ hipError_t launch_cg_xr(hipStream_t, int, int64_t, int, double *, int, const dou
 hipError_t launch_cg_dir(hipStream_t, int, int64_t, int, double *, const double *, const double *, const double *,
                          double *);
 hipError_t launch_dot(hipStream_t, int, int64_t, const double *, const double *, double *);
+// (k_gnn.hip)
+constexpr int GL_NPAR_HOST = 226;
+template <typename T>
+hipError_t launch_gl_heads(hipStream_t, int64_t, int, const T *, const double *, const double *, const double *,
+                           const T *, const uint8_t *, const double *, const float *, const float *, T *, float *);
+template <typename T>
+hipError_t launch_gl_out(hipStream_t, int64_t, int, const T *, const T *, const float *, const T *, const double *,
+                         const double *, const T *, const uint8_t *, T *, T *);
+hipError_t launch_gl_colsums(hipStream_t, int, int64_t, int, const double *, const double *, const double *,
+                             const double *, const uint8_t *, double *);
+hipError_t launch_gl_bwd1(hipStream_t, int, int64_t, int, const double *, const double *, double *, const float *,
+                          const double *, const double *, const double *, const uint8_t *, const double *, double *,
+                          double *);
+hipError_t launch_gl_bwd2(hipStream_t, int, int64_t, int, const double *, const double *, const double *,
+                          const double *, const double *, const double *, const double *, const double *,
+                          const double *, const double *, const uint8_t *, const double *, const float *,
+                          const float *, double *);
+hipError_t launch_gl_adam(hipStream_t, int, const double *, double, float *, float *, float *, float, float, float,
+                          float, int);
+hipError_t launch_gl_node_stats(hipStream_t, int, int64_t, const double *, const double *, const double *, double *);
+hipError_t launch_features(hipStream_t, int64_t, int, const double *, const double *, const double *,
+                           const double *, const double *, float *);
 }  // namespace ofks
 
 using namespace ofks;
@@ -277,6 +299,18 @@ struct ofks_ctx {
     size_t lp_u_bytes = 0;
 
     double *scratch_dev = nullptr;   // this device's copy of `scratch` (ofks_gram_noalloc)
+    // graph learned preconditioner
+    float *gl_W = nullptr, *gl_norm = nullptr;   // 226 weights, 8 standardization constants (device)
+    bool gl_ready = false;
+    float *gl_ft = nullptr;                      // smoothing weights ft of the current block (n x p)
+    size_t gl_ft_cap = 0;
+    double *gl_cap = nullptr;                    // snapshot capture: caller's device buffer of G blocks
+    int64_t gl_cap_every = 1;
+    int32_t gl_cap_max = 0, gl_cap_count = 0;
+    std::vector<double> gl_cap_lam;              // the shifts of each captured block
+    double *gl_work = nullptr;                   // training blocks (5 n x p FP64) and ft (n x p FP32)
+    size_t gl_work_np = 0;
+    std::vector<double> relmin;                  // relmin[j] = lowest rel of X^0..X^j (stall fallback)
 
     // timing
     bool timing = false;
@@ -761,6 +795,16 @@ int pcg_run(ofks_ctx *c, int m, int64_t n, int p, const uint8_t *act, const T *l
     return OFKS_OK;
 }
 
+// the graph form's smoothing weights ft (FP32, n x p), grown when needed
+int ensure_gl_ft(ofks_ctx *c, size_t count) {
+    if (c->gl_ft_cap >= count) return OFKS_OK;
+    if (c->gl_ft) CHK(sync(c));   // queued work may still read the old buffer
+    dfree(c, c->gl_ft);
+    CHK(dalloc(c, &c->gl_ft, count));
+    c->gl_ft_cap = count;
+    return OFKS_OK;
+}
+
 template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) {
     Blocks<T> &B = blk<T>(c);
     const int p = c->p;
@@ -846,7 +890,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     c->L0 = L0;
 
     // energy of X^k (needed before the preconditioner choice in the learned form)
-    const bool learned_form = c->prm.precond == OFKS_PRECOND_LEARNED;
+    const bool learned_form = c->prm.precond == OFKS_PRECOND_LEARNED || c->prm.precond == OFKS_PRECOND_GRAPH;
     double energy = NAN;
     const int ee = learned_form ? 1 : std::max(1, c->prm.energy_every);
     if (scf) {
@@ -877,8 +921,18 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         const size_t W = (size_t)c->prm.fallback_window;
         while (c->ehist.size() > W) c->ehist.erase(c->ehist.begin());
     }
+    // ... or when the fallback_stall iterates before this one did not halve
+    // the lowest residual (a stall while the energy still falls)
+    const int S_stall = c->prm.fallback_stall;
+    const int nr = (int)c->relmin.size();   // iterates evaluated before this one
+    if (learned_form && use_learned && S_stall > 0 && nr > S_stall &&
+        c->relmin[nr - 1] > 0.5 * c->relmin[nr - 1 - S_stall]) {
+        c->lp_hold = std::max(1, c->prm.fallback_hold);
+        use_learned = false;
+        fell_back = 1;
+    }
     const bool use_paper = c->prm.precond == OFKS_PRECOND_PAPER || (learned_form && !use_learned);
-    const int kind = use_learned ? OFKS_PRECOND_LEARNED : (use_paper ? OFKS_PRECOND_PAPER : OFKS_PRECOND_NONE);
+    const int kind = use_learned ? c->prm.precond : (use_paper ? OFKS_PRECOND_PAPER : OFKS_PRECOND_NONE);
 
     std::vector<double> shift(p, 0.0);
     std::vector<uint8_t> neg(p, 0);
@@ -922,6 +976,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     c->last_kkt = kkt;
     c->last_fea = fea;
     c->last_rel = rel;
+    c->relmin.push_back(c->relmin.empty() ? rel : std::min(rel, c->relmin.back()));
     c->last_energy = energy;
     if (st) {
         st->k = c->k;
@@ -946,6 +1001,16 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     if (kind != c->last_kind) c->have_prev = false;   // BB restarts, eta carries over
     c->last_kind = kind;
 
+    // graph-form training snapshots: G of this iterate and its shifts (FP64 plain method)
+    if (c->gl_cap && std::is_same<T, double>::value && use_paper && any_active && c->gl_cap_count < c->gl_cap_max &&
+        c->k % c->gl_cap_every == 0) {
+        double *slot = c->gl_cap + (size_t)c->gl_cap_count * n * p;
+        GradArgs gn{B.HX, slot, B.R, B.D, c->lhd, c->bd, B.lam, c->active, c->part};
+        HIPCHK(launch_rowgemm<T>(c->stream, EPI_GRAD_NORM, n, p, 2 * p, c->gemm_rows, B.BX, B.dinv, B.CC, nullptr, gn,
+                                 &gx));
+        c->gl_cap_lam.insert(c->gl_cap_lam.end(), shift.begin(), shift.end());
+        c->gl_cap_count += 1;
+    }
     // training samples: keep G (and its column norms) before the CG overwrites it
     const bool collect = c->lp_buf && use_paper && any_active && c->lp_count < c->lp_cap;
     if (collect) {
@@ -998,7 +1063,22 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
             c->lp_count += rows * p;
         }
     }
-    if (use_learned) {
+    if (use_learned && c->prm.precond == OFKS_PRECOND_GRAPH) {
+        // P = Z + ft J (G - T Z), Z = exp(fs) J G: heads, one shifted SpMM (Z in D, T Z in HX), sweep
+        if (!c->gl_ready) return fail(c, OFKS_ESTATE, "graph preconditioner: no weights (ofks_gl_set_weights)");
+        CHK(ensure_gl_ft(c, (size_t)n * p));
+        HIPCHK(hipMemcpyAsync(c->g2, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        {
+            Scope sc(c, "graph");
+            HIPCHK(launch_gl_heads<T>(c->stream, n, p, B.P, c->lhd, c->bd, c->hd, B.lam, c->active, c->g2, c->gl_W,
+                                      c->gl_norm, B.D, c->gl_ft));
+        }
+        int used = 0;
+        CHK(spmm_shift<T>(c, p, lbT<T>(c), B.lam, c->active, B.D, B.HX, &used));
+        Scope sc(c, "graph");
+        HIPCHK(launch_gl_out<T>(c->stream, n, p, B.P, B.D, c->gl_ft, B.HX, c->lhd, c->bd, B.lam, c->active, B.P,
+                                (T *)nullptr));
+    } else if (use_learned) {
         if (!c->lp_ready) return fail(c, OFKS_ESTATE, "learned preconditioner: no weights (ofks_lp_set_weights)");
         HIPCHK(hipMemcpyAsync(c->g2, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         Scope sc(c, "mlp");
@@ -1235,6 +1315,7 @@ void ofks_default_params(ofks_params *p) {
     p->fallback_rule = 0;
     p->use_graphs = 1;
     p->algorithm = 0;
+    p->fallback_stall = 30;
 }
 
 int ofks_create(ofks_ctx **out, void *hip_stream) {
@@ -1520,7 +1601,7 @@ int ofks_csr_load(ofks_ctx *c, int64_t n, int64_t nnz, const int64_t *row_ptr, c
 int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
     if (!c || !prm) return OFKS_EINVAL;
     if (!(prm->beta >= 0.0) || !(prm->tol > 0.0) || prm->max_iter < 0 || prm->pcg_iters < 0 ||
-        prm->precond < 0 || prm->precond > 2 || prm->step_rule < 0 || prm->step_rule > 4 ||
+        prm->precond < 0 || prm->precond > 3 || prm->step_rule < 0 || prm->step_rule > 4 ||
         (prm->precision != OFKS_F64 && prm->precision != OFKS_F32) || prm->fallback_rule < 0 ||
         prm->fallback_rule > 1 || prm->algorithm < 0 || prm->algorithm > 1 || prm->spmm_mode < 0 ||
         prm->spmm_mode > 2)
@@ -1530,7 +1611,8 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
     if (prm->scf && !c->assembled) return fail(c, OFKS_ESTATE, "set_params: SCF needs an assembled mesh");
     if (prm->precond == OFKS_PRECOND_PAPER && c->has_system && !c->has_lhalf)
         return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs L/2 (csr_load without Lhalf)");
-    if (prm->precond == OFKS_PRECOND_LEARNED && c->has_system && !c->has_lhalf)
+    if ((prm->precond == OFKS_PRECOND_LEARNED || prm->precond == OFKS_PRECOND_GRAPH) && c->has_system &&
+        !c->has_lhalf)
         return fail(c, OFKS_EINVAL, "set_params: the learned preconditioner needs L/2 (its fallback is the paper's)");
     c->prm = *prm;
     if (c->prm.energy_every < 1) c->prm.energy_every = 1;
@@ -1612,6 +1694,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     c->last_kind = -1;
     c->f32_best = INFINITY;
     c->f32_best_k = 0;
+    c->relmin.clear();
     return sync(c);
 }
 
@@ -2033,6 +2116,269 @@ int ofks_lp_apply(ofks_ctx *c, int32_t p, const double *lam, const double *G, do
     dfree(c, lamd);
     dfree(c, g2);
     dfree(c, neg);
+    return OFKS_OK;
+}
+
+// ---- graph learned preconditioner ---------------------------------------------
+
+namespace {
+// column sums of G^2 into dev g2 (p doubles) for a caller's block of width p
+int col_sq(ofks_ctx *c, int p, const double *G, double *g2) {
+    CHK(ensure_part(c, (size_t)c->grid * p));
+    HIPCHK(launch_coldot<double>(c->stream, c->grid, c->n, p, G, G, c->part));
+    HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, g2));
+    return OFKS_OK;
+}
+
+// device shifts and identity-branch flags for host shifts lam[p]
+int gl_shifts(ofks_ctx *c, int p, const double *lam, double **lamd, uint8_t **neg) {
+    CHK(dalloc(c, lamd, p));
+    CHK(dalloc(c, neg, p));
+    std::vector<double> lv(lam, lam + p);
+    std::vector<uint8_t> nh(p);
+    for (int i = 0; i < p; ++i) nh[i] = lam[i] < 0.0 ? 1 : 0;
+    CHK(upload<double>(c, *lamd, lv));
+    CHK(upload_bytes(c, *neg, nh.data(), p));
+    return OFKS_OK;
+}
+
+// training blocks: Z, QTP, PT, R, dR (FP64) and ft (FP32), each n x p
+int gl_work(ofks_ctx *c, size_t np, double **Z, double **QTP, double **PT, double **Rb, double **dRb, float **FT) {
+    if (c->gl_work_np < np) {
+        if (c->gl_work) CHK(sync(c));
+        dfree(c, c->gl_work);
+        CHK(dalloc(c, &c->gl_work, 5 * np + (np + 1) / 2));
+        c->gl_work_np = np;
+    }
+    *Z = c->gl_work;
+    *QTP = c->gl_work + np;
+    *PT = c->gl_work + 2 * np;
+    *Rb = c->gl_work + 3 * np;
+    *dRb = c->gl_work + 4 * np;
+    *FT = (float *)(c->gl_work + 5 * np);
+    return OFKS_OK;
+}
+
+constexpr int GL_GRID = 256;      // row chunks of the per-column training kernels
+constexpr int GL_BWD_GRID = 512;  // blocks of the parameter-gradient kernel
+
+// Loss and parameter gradient of the graph form's quadratic model for one
+// block G (FP64, n x p) with device shifts lamd / flags neg, at the
+// context's weights.  On return c->red[0..GL_NPAR) holds the gradient sums;
+// *loss the loss.  One host sync for the column weights, one for the loss.
+int gl_loss_grad_dev(ofks_ctx *c, int p, const double *G, const double *lamd, const uint8_t *neg, double *loss,
+                     double *g2w) {
+    const int64_t n = c->n;
+    const size_t np = (size_t)n * p;
+    double *Z, *QTP, *PT, *Rb, *dRb;
+    float *FT;
+    CHK(gl_work(c, np, &Z, &QTP, &PT, &Rb, &dRb, &FT));
+    CHK(ensure_part(c, std::max({(size_t)GL_GRID * 2 * p, (size_t)GL_BWD_GRID * GL_NPAR_HOST,
+                                 (size_t)c->shift_grid * p,
+                                 c->halo_nb ? spmm_halo_part_doubles(c->halo_nb, p) : (size_t)0})));
+    // column sums: g2 for the residual feature, w = 1 / <G, J G>
+    HIPCHK(launch_gl_colsums(c->stream, GL_GRID, n, p, G, c->lhd, c->bd, lamd, neg, c->part));
+    HIPCHK(launch_colsum(c->stream, GL_GRID, 2 * p, c->part, c->red));
+    std::vector<double> cs;
+    CHK(download(c, cs, c->red, 2 * p));
+    std::vector<double> hw(2 * p);
+    for (int l = 0; l < p; ++l) {
+        hw[l] = cs[l];
+        hw[p + l] = cs[p + l] > 0.0 ? 1.0 / cs[p + l] : 0.0;
+    }
+    CHK(upload<double>(c, g2w, hw));   // g2w[0..p) = g2, g2w[p..2p) = w
+    const double *g2 = g2w, *w = g2w + p;
+    int used = 0;
+    // forward: Z, ft; Q = T Z; R = G - Q, P = Z + ft J R
+    HIPCHK(launch_gl_heads<double>(c->stream, n, p, G, c->lhd, c->bd, c->hd, lamd, neg, g2, c->gl_W, c->gl_norm, Z,
+                                   FT));
+    CHK(spmm_shift<double>(c, p, c->lb, lamd, neg, Z, QTP, &used));
+    HIPCHK(launch_gl_out<double>(c->stream, n, p, G, Z, FT, QTP, c->lhd, c->bd, lamd, neg, PT, Rb));
+    // T P, then dP = w (T P - G) (in place) and dR = ft J dP; loss partials
+    CHK(spmm_shift<double>(c, p, c->lb, lamd, neg, PT, QTP, &used));
+    HIPCHK(launch_gl_bwd1(c->stream, GL_GRID, n, p, G, PT, QTP, FT, c->lhd, c->bd, lamd, neg, w, dRb, c->part));
+    HIPCHK(launch_colsum(c->stream, GL_GRID, p, c->part, c->red));
+    std::vector<double> lc;
+    CHK(download(c, lc, c->red, p));
+    double L = 0.0;
+    for (int l = 0; l < p; ++l) L += hw[p + l] * lc[l];
+    *loss = L;
+    // T dR (into PT), then the parameter gradient
+    CHK(spmm_shift<double>(c, p, c->lb, lamd, neg, dRb, PT, &used));
+    HIPCHK(launch_gl_bwd2(c->stream, GL_BWD_GRID, n, p, G, QTP, Rb, Z, dRb, PT, c->lhd, c->bd, c->hd, lamd, neg, g2,
+                          c->gl_W, c->gl_norm, c->part));
+    HIPCHK(launch_colsum(c->stream, GL_BWD_GRID, GL_NPAR_HOST, c->part, c->red));
+    return OFKS_OK;
+}
+}  // namespace
+
+int ofks_gl_set_weights(ofks_ctx *c, const float *w, const float *norm) {
+    if (!c) return OFKS_EINVAL;
+    if (!w || !norm) return fail(c, OFKS_EINVAL, "gl_set_weights: null pointer");
+    for (int i = 0; i < 4; ++i)
+        if (!(norm[4 + i] > 0.0f)) return fail(c, OFKS_EINVAL, "gl_set_weights: feature scales must be > 0");
+    if (!c->gl_W) {
+        CHK(dalloc(c, &c->gl_W, GL_NPAR_HOST));
+        CHK(dalloc(c, &c->gl_norm, 8));
+    }
+    HIPCHK(hipMemcpyAsync(c->gl_W, w, GL_NPAR_HOST * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->gl_norm, norm, 8 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->gl_ready = true;
+    return OFKS_OK;
+}
+
+int ofks_gl_apply(ofks_ctx *c, int32_t p, const double *lam, const double *G, double *P) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "gl_apply: needs L/2 and B");
+    if (!c->gl_ready) return fail(c, OFKS_ESTATE, "gl_apply: no weights");
+    if (p <= 0 || p > 1024 || !lam || !G || !P) return fail(c, OFKS_EINVAL, "gl_apply: bad arguments");
+    if (P == G) return fail(c, OFKS_EINVAL, "gl_apply: P must not alias G");
+    const size_t np = (size_t)c->n * p;
+    double *lamd = nullptr, *g2 = nullptr, *Z = nullptr, *Q = nullptr;
+    uint8_t *neg = nullptr;
+    float *FT = nullptr;
+    CHK(gl_shifts(c, p, lam, &lamd, &neg));
+    CHK(dalloc(c, &g2, p));
+    CHK(dalloc(c, &Z, np));
+    CHK(dalloc(c, &Q, np));
+    CHK(dalloc(c, &FT, np));
+    CHK(ensure_part(c, std::max({(size_t)c->grid * p, (size_t)c->shift_grid * p,
+                                 c->halo_nb ? spmm_halo_part_doubles(c->halo_nb, p) : (size_t)0})));
+    CHK(col_sq(c, p, G, g2));
+    HIPCHK(launch_gl_heads<double>(c->stream, c->n, p, G, c->lhd, c->bd, c->hd, lamd, neg, g2, c->gl_W, c->gl_norm,
+                                   Z, FT));
+    int used = 0;
+    CHK(spmm_shift<double>(c, p, c->lb, lamd, neg, Z, Q, &used));
+    HIPCHK(launch_gl_out<double>(c->stream, c->n, p, G, Z, FT, Q, c->lhd, c->bd, lamd, neg, P, (double *)nullptr));
+    CHK(sync(c));
+    dfree(c, lamd);
+    dfree(c, neg);
+    dfree(c, g2);
+    dfree(c, Z);
+    dfree(c, Q);
+    dfree(c, FT);
+    return OFKS_OK;
+}
+
+int ofks_gl_loss_grad(ofks_ctx *c, int32_t p, const double *lam, const double *G, double *loss, double *grad) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "gl_loss_grad: needs L/2 and B");
+    if (!c->gl_ready) return fail(c, OFKS_ESTATE, "gl_loss_grad: no weights");
+    if (p <= 0 || p > 1024 || !lam || !G || !loss || !grad) return fail(c, OFKS_EINVAL, "gl_loss_grad: bad arguments");
+    double *lamd = nullptr, *g2w = nullptr;
+    uint8_t *neg = nullptr;
+    CHK(gl_shifts(c, p, lam, &lamd, &neg));
+    CHK(dalloc(c, &g2w, 2 * p));
+    CHK(gl_loss_grad_dev(c, p, G, lamd, neg, loss, g2w));
+    std::vector<double> gr;
+    CHK(download(c, gr, c->red, GL_NPAR_HOST));
+    for (int k = 0; k < GL_NPAR_HOST; ++k) grad[k] = gr[k];
+    dfree(c, lamd);
+    dfree(c, neg);
+    dfree(c, g2w);
+    return OFKS_OK;
+}
+
+int ofks_gl_capture(ofks_ctx *c, double *dev_buf, int32_t max_blocks, int64_t every) {
+    if (!c) return OFKS_EINVAL;
+    if (dev_buf && (max_blocks <= 0 || every <= 0)) return fail(c, OFKS_EINVAL, "gl_capture: bad capacity or stride");
+    c->gl_cap = dev_buf;
+    c->gl_cap_max = dev_buf ? max_blocks : 0;
+    c->gl_cap_every = every > 0 ? every : 1;
+    if (dev_buf) {
+        c->gl_cap_count = 0;
+        c->gl_cap_lam.clear();
+    }
+    return OFKS_OK;
+}
+
+int ofks_gl_captured(ofks_ctx *c, int32_t *count, double *host_lam) {
+    if (!c || !count) return OFKS_EINVAL;
+    *count = c->gl_cap_count;
+    if (host_lam) std::memcpy(host_lam, c->gl_cap_lam.data(), c->gl_cap_lam.size() * sizeof(double));
+    return OFKS_OK;
+}
+
+int ofks_gl_train(ofks_ctx *c, int32_t p, const double *dev_G, const double *host_lam, int32_t count,
+                  int32_t epochs, float lr, float *w_inout, float *adam_inout, double *loss_out) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "gl_train: needs L/2 and B");
+    if (!c->gl_ready) return fail(c, OFKS_ESTATE, "gl_train: set the weights and standardization first");
+    if (p <= 0 || p > 1024 || !dev_G || !host_lam || count <= 0 || epochs < 0 || !(lr > 0.0f) || !w_inout ||
+        !adam_inout)
+        return fail(c, OFKS_EINVAL, "gl_train: bad arguments");
+    const int np = GL_NPAR_HOST;
+    HIPCHK(hipMemcpyAsync(c->gl_W, w_inout, np * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    float *m12 = nullptr;
+    double *lamd = nullptr, *g2w = nullptr;
+    uint8_t *neg = nullptr;
+    CHK(dalloc(c, &m12, 2 * np));
+    CHK(dalloc(c, &lamd, p));
+    CHK(dalloc(c, &neg, p));
+    CHK(dalloc(c, &g2w, 2 * p));
+    HIPCHK(hipMemcpyAsync(m12, adam_inout, 2 * np * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    int t = (int)adam_inout[2 * np];
+    const size_t nps = (size_t)c->n * p;
+    for (int e = 0; e < epochs; ++e)
+        for (int j = 0; j < count; ++j) {
+            std::vector<double> lv(host_lam + (size_t)j * p, host_lam + (size_t)(j + 1) * p);
+            std::vector<uint8_t> nh(p);
+            for (int i = 0; i < p; ++i) nh[i] = lv[i] < 0.0 ? 1 : 0;
+            CHK(upload<double>(c, lamd, lv));
+            CHK(upload_bytes(c, neg, nh.data(), p));
+            double L = 0.0;
+            {
+                Scope sc(c, "graph_train");
+                CHK(gl_loss_grad_dev(c, p, dev_G + (size_t)j * nps, lamd, neg, &L, g2w));
+                ++t;
+                HIPCHK(launch_gl_adam(c->stream, np, c->red, 1.0, c->gl_W, m12, m12 + np, lr, 0.9f, 0.999f, 1e-8f,
+                                      t));
+            }
+            if (loss_out) loss_out[(size_t)e * count + j] = L;
+        }
+    HIPCHK(hipMemcpyAsync(w_inout, c->gl_W, np * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(adam_inout, m12, 2 * np * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    adam_inout[2 * np] = (float)t;
+    dfree(c, m12);
+    dfree(c, lamd);
+    dfree(c, neg);
+    dfree(c, g2w);
+    return OFKS_OK;
+}
+
+int ofks_gl_feature_norm(ofks_ctx *c, float *norm_out) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "gl_feature_norm: needs an assembled system");
+    if (!norm_out) return fail(c, OFKS_EINVAL, "gl_feature_norm: null output");
+    const int grid = 256;
+    CHK(ensure_part(c, (size_t)grid * 6));
+    HIPCHK(launch_gl_node_stats(c->stream, grid, c->n, c->lhd, c->bd, c->hd, c->part));
+    HIPCHK(launch_colsum(c->stream, grid, 6, c->part, c->red));
+    std::vector<double> st;
+    CHK(download(c, st, c->red, 6));
+    for (int j = 0; j < 3; ++j) {
+        const double mu = st[j] / (double)c->n;
+        const double var = std::max(0.0, st[3 + j] / (double)c->n - mu * mu);
+        norm_out[j] = (float)mu;
+        norm_out[4 + j] = (float)std::max(1e-3, std::sqrt(var));   // a floor: uniform meshes give var = 0
+    }
+    norm_out[3] = 0.0f;   // g / rms(g) has mean ~0 and unit mean square by construction
+    norm_out[7] = 1.0f;
+    return OFKS_OK;
+}
+
+int ofks_lp_features(ofks_ctx *c, int32_t p, const double *G, float *dev_feat) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system || !c->has_lhalf) return fail(c, OFKS_ESTATE, "lp_features: needs an assembled system");
+    if (p <= 0 || p > 1024 || !G || !dev_feat) return fail(c, OFKS_EINVAL, "lp_features: bad arguments");
+    double *g2 = nullptr;
+    CHK(dalloc(c, &g2, p));
+    CHK(col_sq(c, p, G, g2));
+    HIPCHK(launch_features(c->stream, c->n, p, G, c->lhd, c->bd, c->hd, g2, dev_feat));
+    CHK(sync(c));
+    dfree(c, g2);
     return OFKS_OK;
 }
 

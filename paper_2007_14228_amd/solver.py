@@ -337,6 +337,82 @@ class Solver:
         self._check(self.lib.ofks_lp_apply(self.h, int(G.shape[1]), _np_ptr(lam), _dev_ptr(G), _dev_ptr(P)))
         return P
 
+    def lp_features(self, G):
+        """Raw features [n, p, 4] (float32) of the learned forms for block G."""
+        import torch
+        _check_block(G, self.n)
+        F = torch.empty((self.n, int(G.shape[1]), 4), dtype=torch.float32, device="cuda")
+        self._check(self.lib.ofks_lp_features(self.h, int(G.shape[1]), _dev_ptr(G), _dev_ptr(F, "float32")))
+        return F
+
+    # -- learned graph preconditioner ------------------------------------------
+    def gl_set_weights(self, w: np.ndarray, norm: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        if w.shape != (226,) or norm.shape != (8,):
+            raise ValueError("graph weights: 226 values and 8 standardization constants")
+        self._check(self.lib.ofks_gl_set_weights(self.h, _np_ptr(w), _np_ptr(norm)))
+
+    def gl_apply(self, lam: np.ndarray, G):
+        import torch
+        _check_block(G, self.n)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (int(G.shape[1]),):
+            raise ValueError("lam must have one entry per column")
+        P = torch.empty_like(G)
+        self._check(self.lib.ofks_gl_apply(self.h, int(G.shape[1]), _np_ptr(lam), _dev_ptr(G), _dev_ptr(P)))
+        return P
+
+    def gl_loss_grad(self, lam: np.ndarray, G):
+        _check_block(G, self.n)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        loss = ctypes.c_double()
+        grad = np.empty(226)
+        self._check(self.lib.ofks_gl_loss_grad(self.h, int(G.shape[1]), _np_ptr(lam), _dev_ptr(G),
+                                               ctypes.byref(loss), _np_ptr(grad)))
+        return loss.value, grad
+
+    def gl_capture(self, buf, every: int = 1):
+        """buf: device float64 tensor [slots, n, p] (None stops capturing)."""
+        if buf is None:
+            self._check(self.lib.ofks_gl_capture(self.h, None, 0, 0))
+            self._cap = None
+            return
+        if buf.dim() != 3 or int(buf.shape[1]) != self.n:
+            raise ValueError("capture buffer must be [slots, n, p]")
+        self._cap = buf
+        self._check(self.lib.ofks_gl_capture(self.h, _dev_ptr(buf), int(buf.shape[0]), int(every)))
+
+    def gl_captured(self, p: int):
+        cnt = ctypes.c_int32()
+        self._check(self.lib.ofks_gl_captured(self.h, ctypes.byref(cnt), None))
+        lam = np.empty((max(cnt.value, 1), p))
+        self._check(self.lib.ofks_gl_captured(self.h, ctypes.byref(cnt), _np_ptr(lam)))
+        return cnt.value, lam[: cnt.value]
+
+    def gl_train(self, G, lam: np.ndarray, epochs: int, lr: float, w: np.ndarray, adam: np.ndarray):
+        """Adam over the blocks G [count, n, p] with shifts lam [count, p];
+        returns (weights, optimizer state, losses [epochs, count])."""
+        if G.dim() != 3 or int(G.shape[1]) != self.n:
+            raise ValueError("G must be [count, n, p]")
+        count, p = int(G.shape[0]), int(G.shape[2])
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (count, p):
+            raise ValueError("lam must be [count, p]")
+        w = np.array(w, dtype=np.float32, copy=True)
+        adam = np.array(adam, dtype=np.float32, copy=True)
+        if w.shape != (226,) or adam.shape != (453,):
+            raise ValueError("226 weights and 453 optimizer values")
+        losses = np.empty((epochs, count))
+        self._check(self.lib.ofks_gl_train(self.h, p, _dev_ptr(G), _np_ptr(lam), count, int(epochs),
+                                           ctypes.c_float(lr), _np_ptr(w), _np_ptr(adam), _np_ptr(losses)))
+        return w, adam, losses
+
+    def gl_feature_norm(self) -> np.ndarray:
+        norm = np.empty(8, dtype=np.float32)
+        self._check(self.lib.ofks_gl_feature_norm(self.h, _np_ptr(norm)))
+        return norm
+
     # -- timing ----------------------------------------------------------------
     def timing(self, enable: bool = True):
         self._check(self.lib.ofks_timing(self.h, 1 if enable else 0))

@@ -1,0 +1,235 @@
+"""GPU parity of the graph learned preconditioner (k_gnn.hip, through the C
+ABI) against the oracle's definition (oracle/gnn.py), and of the stall
+fallback of the learned forms.
+
+Tolerances: the network runs in FP32 on the device and FP64 in the oracle, so
+results agree to ~1e-6 relative; the tests use 2e-5 (apply, loss, gradient)
+and 1e-5 on kkt over the first iterations (FP64 blocks), 1e-4 with FP32
+blocks."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import fem, gnn, mlp, pcal
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+NORM = np.array([-1.0, -2.0, -1.0, 0.0, 1.0, 1.5, 2.0, 1.0])
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _weights(seed):
+    """Both heads active: a random output layer, ft around 1/2."""
+    W = gnn.init_weights(seed)
+    rng = np.random.default_rng(seed + 100)
+    W[5 * gnn.H:] = rng.standard_normal(2 * gnn.H + 2) * 0.15
+    W[-1] += 0.5
+    return W.astype(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def graded():
+    Z = np.array([6.0, 1.0, 8.0])
+    R = np.array([[0.3, -0.2, 0.1], [-1.4, 0.9, 0.4], [1.1, 1.3, -0.9]])
+    mesh = wl.graded_mesh(5.0, Z, R, gamma1=0.5, gamma2=1.2, hmin=0.1)
+    w = wl.Workload("graded", mesh, Z, R, p=7, beta=1.0, scf=False, seed=0)
+    d = fem.discretize(mesh, Z, R)
+    return w, d
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = wl.make_workload("c1")
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    return w, d
+
+
+def _solver(w):
+    from paper_2007_14228_amd import Solver
+    s = Solver()
+    s.load_workload(w)
+    return s
+
+
+def _lam(p, seed):
+    lam = -np.random.default_rng(seed).uniform(0.05, 3.0, p)
+    lam[1 % p] = 0.3           # identity branch
+    if p > 2:
+        lam[2] = 0.0           # identity branch (strict inequality)
+    return lam
+
+
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+@pytest.mark.parametrize("p", [3, 70])
+def test_graph_apply_matches_the_oracle(p, mode, graded):
+    w, d = graded
+    print(f"[gpu] graph apply p={p} {mode}", flush=True)
+    s = _solver(w)
+    s.set_params(spmm_mode=mode)
+    W = _weights(1)
+    s.gl_set_weights(W, NORM)
+    G = np.random.default_rng(2).standard_normal((d.n, p))
+    lam = _lam(p, 3)
+    P = s.gl_apply(lam, _dev(G)).cpu().numpy()
+    ref = gnn.apply(W, NORM, d.csr(0.5 * d.L), d.csr(d.B), np.asarray(d.csr(d.H).diagonal()), lam, G)
+    assert _relerr(P, ref) < 2e-5
+    s.close()
+
+
+@pytest.mark.parametrize("p", [3, 70])
+def test_graph_loss_and_gradient_match_the_oracle(p, graded):
+    w, d = graded
+    print(f"[gpu] graph loss/grad p={p}", flush=True)
+    s = _solver(w)
+    W = _weights(4)
+    s.gl_set_weights(W, NORM)
+    G = np.random.default_rng(5).standard_normal((d.n, p))
+    lam = _lam(p, 6)
+    loss, grad = s.gl_loss_grad(lam, _dev(G))
+    rl, rg = gnn.loss_grad(W, NORM, d.csr(0.5 * d.L), d.csr(d.B), np.asarray(d.csr(d.H).diagonal()), lam, G)
+    assert abs(loss - rl) <= 2e-5 * abs(rl)
+    assert np.abs(grad - rg).max() <= 2e-5 * np.abs(rg).max()
+    s.close()
+
+
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+def test_graph_form_follows_the_oracle_then_converges(mode, c1):
+    """First iterations of the graph form (fallbacks off) against the
+    oracle's, through each SpMM kernel; then, fallbacks on, convergence to
+    the dense eigenvalues."""
+    w, d = c1
+    print(f"[gpu] graph pcal {mode}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    W = _weights(11)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    off = dict(fallback_window=0, fallback_stall=0)
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=5, precond="graph",
+                                              lp_weights=(W, NORM), **off))
+    s = _solver(w)
+    s.gl_set_weights(W, NORM)
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=5, precond="graph", spmm_mode=mode, energy_every=1, **off)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, _, _ = s.step(6)
+    assert len(st) == len(hist) == 6
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-5 * b.kkt, (a, b)
+    assert all(x["precond_used"] == 3 for x in st[:-1] if x["k"] > 0)
+    s.set_params(beta=w.beta, tol=1e-10, max_iter=3000, precond="graph", spmm_mode=mode)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, done, _ = s.step(3000)
+    assert done and st[-1]["rel"] < 1e-10
+    ref = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p]
+    assert abs(st[-1]["energy"] - sum(ref)) < 1e-9 * abs(sum(ref))
+    s.close()
+
+
+@pytest.mark.parametrize("p", [40, 130])
+def test_graph_form_with_fp32_blocks(p, c1):
+    """The FP32 heads and sweep (and the FP32 shifted SpMM) over the first
+    iterations, against the FP64 oracle: kkt to 1e-4."""
+    w, d = c1
+    print(f"[gpu] graph fp32 p={p}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    W = _weights(12)
+    X0 = pcal.chol_gs(prob, wl.random_block(7, d.n, p))
+    off = dict(fallback_window=0, fallback_stall=0)
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=3, precond="graph",
+                                              lp_weights=(W, NORM), **off))
+    s = _solver(w)
+    s.gl_set_weights(W, NORM)
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=3, precond="graph", precision="f32", refine_tol=0.0,
+                 energy_every=1, **off)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, _, _ = s.step(4)
+    assert st[0]["precision"] == 1
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-4 * b.kkt, (a, b)
+    s.close()
+
+
+def test_graph_training_on_captured_blocks_lowers_the_loss(c1):
+    """Snapshots of G from the plain method's iterates, then Adam on the
+    quadratic model: the loss falls, and the loss the training reports for a
+    block equals ofks_gl_loss_grad at the same weights."""
+    import torch
+    w, d = c1
+    print("[gpu] graph training", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    # the oracle's gradient G and shifts at every iterate (eq. lambda2 multiplier)
+    ref = {}
+
+    def grab(k, X, HX, BX, S, L0):
+        Lam = pcal.multiplier(S, L0, w.beta)
+        ref[k] = (HX + BX @ (w.beta * (S - np.eye(w.p)) - Lam), np.diag(Lam).copy())
+
+    pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=14, precond="paper"), callback=grab)
+    s = _solver(w)
+    buf = torch.zeros((6, d.n, w.p), dtype=torch.float64, device="cuda")
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=14, precond="paper")
+    s.gl_capture(buf, every=2)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    s.step(15)
+    count, lam = s.gl_captured(w.p)
+    s.gl_capture(None)
+    assert 3 <= count <= 6 and np.all(np.any(lam < 0, axis=1))
+    # the captured blocks are the gradients of the even iterates with a negative shift
+    ks = [k for k in range(0, 15, 2) if np.any(ref[k][1] < 0)][:count]
+    Gc = buf[:count]
+    for j, k in enumerate(ks):
+        assert _relerr(Gc[j].cpu().numpy(), ref[k][0]) < 1e-9, k
+        assert np.allclose(lam[j], ref[k][1], rtol=1e-9, atol=1e-12)
+    norm = s.gl_feature_norm()
+    assert np.all(norm[4:] > 0)
+    W0 = gnn.init_weights(0).astype(np.float32)
+    s.gl_set_weights(W0, norm)
+    l0, _ = s.gl_loss_grad(lam[0], Gc[0].contiguous())
+    Wt, adam, losses = s.gl_train(Gc.contiguous(), lam, epochs=40, lr=3e-3, w=W0, adam=np.zeros(453))
+    assert abs(losses[0, 0] - l0) <= 1e-10 * abs(l0)
+    assert losses[-1].mean() < losses[0].mean()
+    assert adam[-1] == 40 * count
+    s.close()
+
+
+def test_stalled_learned_form_falls_back_on_the_gpu(c1):
+    """The stall rule on the device: a pointwise network whose scale follows
+    the residual feature makes BB crawl without an energy rise (the oracle
+    stays at rel ~3e-2 for 600 iterations without the rule).  With the
+    energy rule off and the stall rule on, the first iterations follow the
+    oracle's, the device falls back and the run converges."""
+    w, d = c1
+    print("[gpu] stall fallback", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    W = np.zeros(mlp.NPAR)
+    W[3] = 3.0
+    W[5 * mlp.H] = 3.0
+    norm = np.array([0, 0, 0, 0, 1, 1, 1, 1.0])
+    prm = dict(beta=w.beta, tol=1e-9, precond="learned", fallback_window=0, fallback_stall=10)
+    _, hist = pcal.pcal(prob, X0, pcal.Params(max_iter=4, lp_weights=(W, norm), **prm))
+    s = _solver(w)
+    s.lp_set_weights(W, norm.astype(np.float32))
+    s.set_params(max_iter=4, energy_every=1, **prm)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, _, _ = s.step(5)
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-5 * b.kkt, (a, b)
+    s.set_params(max_iter=1500, **prm)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, done, _ = s.step(1500)
+    assert done and st[-1]["rel"] < 1e-9
+    assert sum(x["fell_back"] for x in st) >= 1
+    ref = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p]
+    assert abs(st[-1]["energy"] - sum(ref)) < 1e-8 * abs(sum(ref))
+    s.close()

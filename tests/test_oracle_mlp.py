@@ -111,3 +111,28 @@ def test_energy_samples_give_the_T_norm_error_for_a_constant_scale():
     assert np.array_equal(Sc[:, :, 6], np.maximum(S[:, :, 6], 0.0))
     # the identity-branch column: T = I, J = 1, so every target is 1
     assert np.allclose(S[:, 1, 5], 1.0)
+
+
+def test_stalled_learned_form_falls_back_by_the_stall_rule():
+    """A network whose scale depends strongly on the residual feature makes
+    the preconditioned step nonlinear in G: BB crawls (rel still ~3e-2 after
+    600 iterations) while the energy does not rise, so the energy rule never
+    fires.  The stall rule (the last S iterates did not halve the lowest
+    residual) hands the iteration to the paper preconditioner for
+    fallback_hold steps at a time, and the run converges."""
+    import json, os
+    w = wl.make_workload("c1")
+    d = fem.discretize(w.mesh, w.Z, w.R)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(0, d.n, w.p))
+    W = np.zeros(mlp.NPAR)
+    W[3] = 3.0                 # hidden unit 0 reads the residual feature
+    W[5 * mlp.H] = 3.0         # and drives the log-scale
+    norm = np.array([0, 0, 0, 0, 1, 1, 1, 1.0])
+    prm = dict(beta=w.beta, tol=1e-9, max_iter=600, precond="learned", lp_weights=(W, norm), fallback_window=0)
+    _, stuck = pcal.pcal(prob, X0, pcal.Params(fallback_stall=0, **prm))
+    assert len(stuck) == 601 and stuck[-1].rel > 1e-2
+    _, hist = pcal.pcal(prob, X0, pcal.Params(fallback_stall=10, **prm))
+    assert hist[-1].rel < 1e-9
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_dense_eigs.json")))
+    assert abs(hist[-1].energy - sum(ref["eigenvalues"][: w.p])) < 1e-8
