@@ -183,6 +183,31 @@ int ofks_get_x(ofks_ctx *ctx, double *dev_X);
  * current iterate, dev_rho device f64[n_tets*4]. */
 int ofks_get_density(ofks_ctx *ctx, double *dev_rho);
 
+/* Density/potential update (Sections 2.1-2.2): for the current iterate X^k,
+ * the density rho = f sum_l psi_l^2 at the quadrature points, the LDA
+ * exchange-correlation, the Hartree potential (L U = 4 pi b, warm-started
+ * CG) and H(X) = L/2 + M(V_ext + V_H + v_xc), re-assembled in place.  The SCF
+ * iteration does this at the start of every step; this call lets a caller
+ * refresh H between steps of a fixed-H run.  ESTATE without an assembled
+ * mesh or before ofks_set_x0; EZERONORM for a zero column. */
+int ofks_update_density(ofks_ctx *ctx);
+
+/* ---- checkpoint / resume ---------------------------------------------------
+ * The iteration state after any number of steps: the current, previous and
+ * previous-preconditioned blocks (the BB pair), the deferred column
+ * normalization, k, eta, eta_0, kkt_0, the fallback and precision-switch
+ * state, and (SCF) the Hartree potential that warm-starts the next solve.
+ * ofks_state_get writes it into a caller-owned device buffer of at least
+ * ofks_state_size bytes (the size grows by 8 bytes per iteration);
+ * ofks_state_set restores it on a context with the same system and
+ * parameters (and, for the learned forms, the same weights), allocating the
+ * blocks for its width and precision; the following steps are bit-identical
+ * to those of the uninterrupted run.  EINVAL for a buffer too small, a state
+ * of another size or SCF mode, or one not written by ofks_state_get. */
+int ofks_state_size(ofks_ctx *ctx, size_t *bytes);
+int ofks_state_get(ofks_ctx *ctx, void *dev_buf, size_t bytes);
+int ofks_state_set(ofks_ctx *ctx, const void *dev_buf, size_t bytes);
+
 /* ---- single kernels, for parity checks ----------------------------------- */
 
 /* HX = H X and BX = B X (dual SpMM) on the current system; device f64 blocks n x p. */

@@ -82,6 +82,10 @@ SIGNATURES = [
     ("ofks_postprocess", I32, [P, P]),
     ("ofks_get_x", I32, [P, P]),
     ("ofks_get_density", I32, [P, P]),
+    ("ofks_update_density", I32, [P]),
+    ("ofks_state_size", I32, [P, ctypes.POINTER(ctypes.c_size_t)]),
+    ("ofks_state_get", I32, [P, P, ctypes.c_size_t]),
+    ("ofks_state_set", I32, [P, P, ctypes.c_size_t]),
     ("ofks_spmm", I32, [P, I32, P, P, P]),
     ("ofks_spmm_ex", I32, [P, I32, I32, I32, P, P, P, P]),
     ("ofks_gram", I32, [P, I32, P, P, P, P, P]),

@@ -31,7 +31,7 @@ constexpr int GL_NPAR = 4 * GL_H + GL_H + 2 * GL_H + 2;   // 226
 __device__ __forceinline__ float gl_tanh(float x) {
     // tanh x = 1 - 2 / (exp(2x) + 1); saturates correctly for large |x|
     const float e = __expf(2.0f * x);
-    return 1.0f - 2.0f / (e + 1.0f);
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
 // Both heads for standardized x; the hidden layer into h when KEEP.
@@ -69,6 +69,13 @@ __device__ __forceinline__ float gl_resid_feature(float g, float rms, const floa
 // Z = exp(fs) J G and FT = ft for every (row, column); rows handled by
 // 2^lpr_log2 lanes that stride over the columns (the block kernels' mapping).
 // g2[c] = sum_i g_ic^2 (FP64).
+//
+// The same arithmetic as gl_forward, arranged for the VALU: the row-only part
+// of the first layer is formed once per row (a_k = W1[k,0:3] x_node + b1_k),
+// leaving one FMA per hidden unit and column; the hidden pre-activations are
+// pre-scaled by 2 log2(e), so tanh z = 1 - 2 / (2^(2 log2(e) z) + 1) takes one
+// exp2, one add and one hardware reciprocal; and sum_k W2_k tanh_k is summed
+// as sum_k W2_k - 2 sum_k W2_k / (2^(...) + 1).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gl_heads(int64_t n, int p, int lpr_log2, const T *__restrict__ G,
                                                  const double *__restrict__ lhd, const double *__restrict__ bd,
@@ -80,16 +87,37 @@ __global__ __launch_bounds__(256) void k_gl_heads(int64_t n, int p, int lpr_log2
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lpr_log2;
     const int lane = threadIdx.x & (lpr - 1);
     if (row >= n) return;
+    const float *W1 = W, *b1 = W + 4 * GL_H, *W2 = W + 5 * GL_H, *b2 = W + 7 * GL_H;
+    constexpr float K2 = 2.0f * 1.4426950408889634f;   // 2 log2(e)
     const double l2 = lhd[row], b = bd[row];
-    float x[4];
+    float x[3];
     gl_node(l2, b, hd[row], norm, x);
+    float a[GL_H];
+    float s0 = b2[0], s1 = b2[1];
+#pragma unroll
+    for (int k = 0; k < GL_H; ++k) {
+        float z = b1[k];
+        z = fmaf(W1[4 * k + 0], x[0], z);
+        z = fmaf(W1[4 * k + 1], x[1], z);
+        z = fmaf(W1[4 * k + 2], x[2], z);
+        a[k] = K2 * z;
+        s0 += W2[k];
+        s1 += W2[GL_H + k];
+    }
     for (int c = lane; c < p; c += lpr) {
         const T g = G[row * p + c];
-        x[3] = gl_resid_feature((float)g, (float)sqrt(g2[c] / (double)n), norm);
-        float fs, ft;
-        gl_forward<false>(W, x, fs, ft, nullptr);
+        const float x3 = gl_resid_feature((float)g, (float)sqrt(g2[c] / (double)n), norm);
+        float r0 = 0.0f, r1 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < GL_H; ++k) {
+            const float z2 = fmaf(K2 * W1[4 * k + 3], x3, a[k]);
+            const float r = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z2) + 1.0f);
+            r0 = fmaf(W2[k], r, r0);
+            r1 = fmaf(W2[GL_H + k], r, r1);
+        }
+        const float fs = fmaf(-2.0f, r0, s0), ft = fmaf(-2.0f, r1, s1);
         const T J = negl[c] ? T(1) / (T(l2) - lam[c] * T(b)) : T(1);
-        Z[row * p + c] = (T)__expf(fs) * J * g;
+        Z[row * p + c] = (T)__builtin_amdgcn_exp2f(1.4426950408889634f * fs) * J * g;
         FT[row * p + c] = ft;
     }
 }

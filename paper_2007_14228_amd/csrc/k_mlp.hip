@@ -25,7 +25,7 @@ constexpr int LP_SAMPLE = 8;                         // floats per training samp
 __device__ __forceinline__ float fast_tanh(float x) {
     // tanh x = 1 - 2 / (exp(2x) + 1); saturates correctly for large |x|
     const float e = __expf(2.0f * x);
-    return 1.0f - 2.0f / (e + 1.0f);
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
 // f(x) for standardized x; params in global memory (uniform across lanes)

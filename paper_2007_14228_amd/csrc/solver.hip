@@ -2382,6 +2382,213 @@ int ofks_lp_features(ofks_ctx *c, int32_t p, const double *G, float *dev_feat) {
     return OFKS_OK;
 }
 
+// ---- checkpoint / resume -------------------------------------------------------
+
+extern "C++" {
+namespace {
+constexpr uint64_t STATE_MAGIC = 0x5441545346534b4fULL;   // "OKSFSTAT"
+constexpr int32_t STATE_VERSION = 1;
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t version, prec, p, scf;
+    int64_t n;
+    int32_t k, have_prev, lp_hold, last_kind, f32_best_k, done, n_ehist, n_relmin, n_sl, pad;
+    double kkt0, eta, eta0, f32_best, last_kkt, last_fea, last_rel, last_energy;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// bytes of the host part (header and vectors) and of one block
+size_t state_host_bytes(ofks_ctx *c) {
+    return align256(sizeof(StateHeader) +
+                    8 * ((size_t)c->p + c->ehist.size() + c->relmin.size() + c->S.size() + c->L0.size()));
+}
+size_t state_block_bytes(ofks_ctx *c) {
+    return (size_t)c->n * c->p * (c->prec == OFKS_F64 ? sizeof(double) : sizeof(float));
+}
+
+template <typename T> int state_blocks(ofks_ctx *c, char *buf, size_t off, bool get) {
+    Blocks<T> &B = blk<T>(c);
+    const size_t bb = (size_t)c->n * c->p * sizeof(T);
+    T *blocks[3] = {B.Xt, B.Xp, B.Pp};
+    for (int i = 0; i < 3; ++i) {
+        char *d = buf + off + i * align256(bb);
+        if (get) HIPCHK(hipMemcpyAsync(d, blocks[i], bb, hipMemcpyDeviceToDevice, c->stream));
+        else HIPCHK(hipMemcpyAsync(blocks[i], d, bb, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return OFKS_OK;
+}
+
+// (re)allocates the iteration blocks for width p in precision prec (the
+// allocation part of ofks_set_x0, without a start block)
+int setup_blocks(ofks_ctx *c, int p, int prec) {
+    free_blocks<double>(c);
+    free_blocks<float>(c);
+    dfree(c, c->active);
+    dfree(c, c->rz);
+    dfree(c, c->g2);
+    dfree(c, c->tw);
+    c->p = p;
+    c->prec = prec;
+    CHK(dalloc(c, &c->active, p));
+    CHK(dalloc(c, &c->rz, p));
+    CHK(dalloc(c, &c->g2, p));
+    CHK(dalloc(c, &c->tw, p));
+    CHK(ensure_part(c, partials_needed(c, p)));
+    if (prec == OFKS_F64) {
+        CHK(alloc_blocks<double>(c));
+    } else {
+        CHK(ensure_f32_matrices(c));
+        CHK(alloc_blocks<float>(c));
+    }
+    return OFKS_OK;
+}
+
+// H(X) for the stored iterate: column B-norms of X~ (the deferred
+// normalization), then density, xc, Hartree and re-assembly
+template <typename T> int update_density_t(ofks_ctx *c) {
+    Blocks<T> &B = blk<T>(c);
+    const int p = c->p;
+    std::vector<double> dn(p, 1.0);
+    if (c->prm.algorithm != 1) {
+        CHK(spmm_pair<T>(c, p, hbT<T>(c), B.Xt, B.BX, nullptr, 1));
+        std::vector<double> d2;
+        CHK(coldot<T>(c, B.Xt, B.BX, d2));
+        for (int i = 0; i < p; ++i) {
+            if (!(d2[i] > 0.0)) return fail(c, OFKS_EZERONORM, "update_density: column %d has zero B-norm", i);
+            dn[i] = 1.0 / std::sqrt(d2[i]);
+        }
+    }
+    CHK(upload<T>(c, B.dinv, dn));
+    return build_h<T>(c, B.Xt, B.dinv);
+}
+}  // namespace
+}  // extern "C++"
+
+int ofks_state_size(ofks_ctx *c, size_t *bytes) {
+    CHK(check_ready(c));
+    if (!bytes) return fail(c, OFKS_EINVAL, "state_size: null output");
+    *bytes = state_host_bytes(c) + 3 * align256(state_block_bytes(c)) + (c->prm.scf ? 8 * (size_t)c->n : 0);
+    return OFKS_OK;
+}
+
+int ofks_state_get(ofks_ctx *c, void *dev_buf, size_t bytes) {
+    CHK(check_ready(c));
+    size_t need = 0;
+    CHK(ofks_state_size(c, &need));
+    if (!dev_buf || bytes < need) return fail(c, OFKS_EINVAL, "state_get: need a device buffer of %zu bytes", need);
+    StateHeader h{};
+    h.magic = STATE_MAGIC;
+    h.version = STATE_VERSION;
+    h.prec = c->prec;
+    h.p = c->p;
+    h.scf = c->prm.scf ? 1 : 0;
+    h.n = c->n;
+    h.k = c->k;
+    h.have_prev = c->have_prev ? 1 : 0;
+    h.lp_hold = c->lp_hold;
+    h.last_kind = c->last_kind;
+    h.f32_best_k = c->f32_best_k;
+    h.done = c->done ? 1 : 0;
+    h.n_ehist = (int32_t)c->ehist.size();
+    h.n_relmin = (int32_t)c->relmin.size();
+    h.n_sl = (int32_t)c->S.size();
+    h.kkt0 = c->kkt0;
+    h.eta = c->eta;
+    h.eta0 = c->eta0;
+    h.f32_best = c->f32_best;
+    h.last_kkt = c->last_kkt;
+    h.last_fea = c->last_fea;
+    h.last_rel = c->last_rel;
+    h.last_energy = c->last_energy;
+    const size_t hb = state_host_bytes(c);
+    std::vector<char> host(hb, 0);
+    std::memcpy(host.data(), &h, sizeof h);
+    double *v = (double *)(host.data() + sizeof h);
+    for (double x : c->dinv_h) *v++ = x;
+    for (double x : c->ehist) *v++ = x;
+    for (double x : c->relmin) *v++ = x;
+    for (double x : c->S) *v++ = x;
+    for (double x : c->L0) *v++ = x;
+    char *buf = (char *)dev_buf;
+    CHK(upload_bytes(c, buf, host.data(), hb));
+    if (c->prec == OFKS_F64) CHK(state_blocks<double>(c, buf, hb, true));
+    else CHK(state_blocks<float>(c, buf, hb, true));
+    if (c->prm.scf)
+        HIPCHK(hipMemcpyAsync(buf + hb + 3 * align256(state_block_bytes(c)), c->U, 8 * (size_t)c->n,
+                              hipMemcpyDeviceToDevice, c->stream));
+    return sync(c);
+}
+
+int ofks_state_set(ofks_ctx *c, const void *dev_buf, size_t bytes) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "state_set: no system");
+    if (!c->has_params) return fail(c, OFKS_ESTATE, "state_set: call ofks_set_params first");
+    if (!dev_buf || bytes < sizeof(StateHeader)) return fail(c, OFKS_EINVAL, "state_set: buffer too small");
+    StateHeader h{};
+    HIPCHK(hipMemcpyAsync(&h, dev_buf, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (h.magic != STATE_MAGIC || h.version != STATE_VERSION)
+        return fail(c, OFKS_EINVAL, "state_set: not a state written by ofks_state_get");
+    if (h.n != c->n) return fail(c, OFKS_EINVAL, "state_set: state is for n = %lld, system has n = %lld",
+                                 (long long)h.n, (long long)c->n);
+    if (h.p <= 0 || h.p > 1024 || (h.prec != OFKS_F64 && h.prec != OFKS_F32) || h.n_ehist < 0 || h.n_relmin < 0 ||
+        h.n_sl < 0 || h.n_sl > 1024 * 1024)
+        return fail(c, OFKS_EINVAL, "state_set: corrupt header");
+    if ((h.scf != 0) != (c->prm.scf != 0))
+        return fail(c, OFKS_EINVAL, "state_set: the state's SCF mode differs from the parameters'");
+    if (h.scf && !c->assembled) return fail(c, OFKS_ESTATE, "state_set: an SCF state needs an assembled mesh");
+    const size_t hb = align256(sizeof h + 8 * ((size_t)h.p + h.n_ehist + h.n_relmin + 2 * (size_t)h.n_sl));
+    const size_t bb = (size_t)h.n * h.p * (h.prec == OFKS_F64 ? sizeof(double) : sizeof(float));
+    const size_t need = hb + 3 * align256(bb) + (h.scf ? 8 * (size_t)h.n : 0);
+    if (bytes < need) return fail(c, OFKS_EINVAL, "state_set: buffer holds %zu bytes, the state %zu", bytes, need);
+    std::vector<char> host(hb);
+    HIPCHK(hipMemcpyAsync(host.data(), dev_buf, hb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(setup_blocks(c, h.p, h.prec));
+    const double *v = (const double *)(host.data() + sizeof h);
+    c->dinv_h.assign(v, v + h.p);
+    v += h.p;
+    c->ehist.assign(v, v + h.n_ehist);
+    v += h.n_ehist;
+    c->relmin.assign(v, v + h.n_relmin);
+    v += h.n_relmin;
+    c->S.assign(v, v + h.n_sl);
+    v += h.n_sl;
+    c->L0.assign(v, v + h.n_sl);
+    char *buf = (char *)dev_buf;
+    if (h.prec == OFKS_F64) CHK(state_blocks<double>(c, buf, hb, false));
+    else CHK(state_blocks<float>(c, buf, hb, false));
+    if (h.scf)
+        HIPCHK(hipMemcpyAsync(c->U, buf + hb + 3 * align256(bb), 8 * (size_t)h.n, hipMemcpyDeviceToDevice,
+                              c->stream));
+    c->k = h.k;
+    c->have_prev = h.have_prev != 0;
+    c->lp_hold = h.lp_hold;
+    c->last_kind = h.last_kind;
+    c->f32_best_k = h.f32_best_k;
+    c->done = h.done != 0;
+    c->kkt0 = h.kkt0;
+    c->eta = h.eta;
+    c->eta0 = h.eta0;
+    c->f32_best = h.f32_best;
+    c->last_kkt = h.last_kkt;
+    c->last_fea = h.last_fea;
+    c->last_rel = h.last_rel;
+    c->last_energy = h.last_energy;
+    c->has_x = true;
+    return sync(c);
+}
+
+int ofks_update_density(ofks_ctx *c) {
+    CHK(check_ready(c));
+    if (!c->assembled) return fail(c, OFKS_ESTATE, "update_density: needs an assembled mesh");
+    if (c->prec == OFKS_F64) CHK(update_density_t<double>(c));
+    else CHK(update_density_t<float>(c));
+    return sync(c);
+}
+
 int ofks_timing(ofks_ctx *c, int32_t enable) {
     if (!c) return OFKS_EINVAL;
     CHK(sync(c));

@@ -216,6 +216,23 @@ class Solver:
         self._check(self.lib.ofks_get_density(self.h, _dev_ptr(rho)))
         return rho
 
+    def update_density(self):
+        self._check(self.lib.ofks_update_density(self.h))
+
+    def state_get(self):
+        """The iteration state as a device uint8 tensor (checkpoint)."""
+        import torch
+        nb = ctypes.c_size_t()
+        self._check(self.lib.ofks_state_size(self.h, ctypes.byref(nb)))
+        buf = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        self._check(self.lib.ofks_state_get(self.h, ctypes.c_void_p(buf.data_ptr()), nb.value))
+        return buf
+
+    def state_set(self, buf):
+        if not buf.is_cuda or buf.dtype != __import__("torch").uint8 or not buf.is_contiguous():
+            raise TypeError("state must be a contiguous device uint8 tensor")
+        self._check(self.lib.ofks_state_set(self.h, ctypes.c_void_p(buf.data_ptr()), int(buf.numel())))
+
     # -- single kernels -------------------------------------------------------
     def spmm(self, X):
         import torch
