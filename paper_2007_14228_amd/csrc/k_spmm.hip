@@ -466,13 +466,16 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t n, const int64_t *__re
 // block, and the waves per SIMD the register budget is cut for (set by how
 // many blocks the LDS admits per CU).
 #ifndef OFKS_HALO_MAX
-#define OFKS_HALO_MAX 80
+#define OFKS_HALO_MAX 76   // with the DMA kernel's separate dot area, three blocks still fit a CU's LDS
 #endif
 #ifndef OFKS_HALO_RMAX
 #define OFKS_HALO_RMAX 16   // an 80-row halo holds about 16 Morton-ordered rows' neighbours anyway
 #endif
 #ifndef OFKS_HALO_WAVES
 #define OFKS_HALO_WAVES 8
+#endif
+#ifndef OFKS_HALO_DMA
+#define OFKS_HALO_DMA 1   // 0: stage every slice through registers (the unaligned-row kernel)
 #endif
 #ifndef OFKS_HALO_WPE
 #define OFKS_HALO_WPE 6
@@ -697,6 +700,222 @@ __global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu
     }
 }
 
+// The same products for blocks whose rows of X are 16-byte aligned, with the
+// halo staged by the direct global-to-LDS loads of gfx950
+// (global_load_lds_dwordx4): lane t of a wave instruction writes its 16 bytes
+// at the wave's LDS base + 16 t, so a wave fills two consecutive 512-byte
+// halo slots (lanes 0-31, 32-63) without passing the data through registers.
+// The next slice's loads are issued as soon as every wave has consumed the
+// current one, before this slice's results are stored, so the stores stay in
+// flight while a wave waits only for its own loads (vector memory operations
+// complete in issue order).  The shifted product's per-wave dot partials have
+// an LDS area of their own.  Per slice: wait for the own loads, barrier,
+// compute, barrier, issue the next slice, store, sum the partials.
+// Columns at or past p in a ragged last slice stage in-bounds data of the
+// row's first segment; no output reads them (each lane's columns are
+// independent).
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * HALO_WAVES) __attribute__((amdgpu_waves_per_eu(OFKS_HALO_WPE))) void
+k_spmm_halo_dma(int64_t nb, int p, const int64_t *__restrict__ row0, const int64_t *__restrict__ hoff,
+                const int32_t *__restrict__ halo, const int32_t *__restrict__ rbase, const int64_t *__restrict__ brp,
+                const uint16_t *__restrict__ lcol, const typename pair_t<T>::type *__restrict__ w,
+                const T *__restrict__ X, T *__restrict__ Y1, T *__restrict__ Y2, int sel, const T *__restrict__ lam,
+                const uint8_t *__restrict__ active, double *__restrict__ part) {
+    using P2 = typename pair_t<T>::type;
+    constexpr int CP = 512 / sizeof(T);   // columns per slice
+    constexpr int VW = 16 / sizeof(T);    // one 16-byte segment
+    constexpr int LPC = CP / 64;          // columns per lane in a slice
+    constexpr int SEG = CP / VW;          // 32 segments per slot
+    constexpr int SST = 64 * HALO_WAVES / SEG;
+    constexpr int SPT = (HALO_MAX + SST - 1) / SST;
+    static_assert(SEG == 32, "a wave instruction fills two slots");
+    static_assert(SST == HALO_SST && SPT * SST == HALO_STRIDE, "padded halo stride");
+    // an instruction is issued only when its first (even) slot is below the
+    // halo size <= HALO_MAX, so with HALO_MAX even it never writes past it
+    static_assert(HALO_MAX % 2 == 0, "even halo capacity");
+    __shared__ T Xs[HALO_MAX * CP];
+    __shared__ int ent_off[HALO_WAVES][64];
+    __shared__ P2 ent_w[HALO_WAVES][64];
+    __shared__ double red[MODE == 1 ? HALO_WAVES * CP : 1];
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (b >= nb) {
+        if (MODE == 1)
+            for (int c = threadIdx.x; c < p; c += blockDim.x) part[b * p + c] = 0.0;
+        return;
+    }
+    const int sg = threadIdx.x % SEG, ss = threadIdx.x / SEG;   // ss = 2 wave + lane / 32
+    int hrow[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) hrow[u] = halo[b * HALO_STRIDE + ss + SST * u];
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t r0 = row0[b], r1 = row0[b + 1];
+    const int hn = (int)(hoff[b + 1] - hoff[b]);
+    const int rb = MODE == 1 ? rbase[b] : 0;
+    // the wave's rows' entries, loaded with the halo rows; both are pinned in
+    // registers before the first halo load is issued (empty asm operands: no
+    // instruction), so the compiler neither sinks these loads into the slice
+    // loop nor waits between the halo loads (a value loaded before an LDS
+    // load that is still in flight is otherwise waited for with vmcnt(0))
+    int len[HALO_RPW];
+    int lc[HALO_RPW];
+    P2 we[HALO_RPW];
+    const int64_t *bp = brp + b * HALO_BRP;
+#pragma unroll
+    for (int i = 0; i < HALO_RPW; ++i) {
+        const int k = wave + HALO_WAVES * i;
+        const int64_t e0 = bp[k];
+        len[i] = (int)(bp[k + 1] - e0);
+        const int64_t e = lane < len[i] ? e0 + lane : 0;
+        we[i] = w[e];
+        lc[i] = (int)lcol[e];
+    }
+    // staging of the slice at columns c0: wave instruction u fills slots
+    // SST u + 2 wave and + 1; instructions wholly past the halo are skipped.
+    // All addresses are formed before the first load is issued.
+    int64_t hoffs[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+        hoffs[u] = (int64_t)hrow[u] * p;
+        asm volatile("" : "+v"(hoffs[u]));
+    }
+#pragma unroll
+    for (int i = 0; i < HALO_RPW; ++i) asm volatile("" : "+v"(lc[i]), "+v"(we[i].x), "+v"(we[i].y));
+    auto stage = [&](int c0) {
+        const int c = c0 + sg * VW;
+        const int cc = c < p ? c : 0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int s0 = SST * u + 2 * wave;
+            if (s0 < hn)
+                __builtin_amdgcn_global_load_lds((const void *)(X + hoffs[u] + cc),
+                                                 (__attribute__((address_space(3))) void *)(Xs + s0 * CP), 16, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    stage(0);
+    for (int c0 = 0; c0 < p; c0 += CP) {
+        T lm[LPC];
+        bool on[LPC];
+#pragma unroll
+        for (int j = 0; j < LPC; ++j) {
+            const int c = c0 + lane + 64 * j;
+            lm[j] = (MODE == 1 && c < p) ? lam[c] : T(0);
+            on[j] = (MODE == 1 && c < p) ? active[c] != 0 : false;
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // this thread's loads (and everything before them)
+        __builtin_amdgcn_s_barrier();    // every wave's: the slice is in LDS
+        __builtin_amdgcn_sched_barrier(0);
+        T q1[HALO_RPW][LPC], q2[HALO_RPW][LPC];
+        double dot[LPC];
+#pragma unroll
+        for (int j = 0; j < LPC; ++j) dot[j] = 0.0;
+#pragma unroll
+        for (int i = 0; i < HALO_RPW; ++i) {
+            const int64_t row = r0 + wave + HALO_WAVES * i;
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) { q1[i][j] = T(0); q2[i][j] = T(0); }
+            if (row >= r1) continue;
+            T dv[LPC];
+            if (MODE == 1) {
+#pragma unroll
+                for (int j = 0; j < LPC; ++j) dv[j] = Xs[(rb + (int)(row - r0)) * CP + lane + 64 * j];
+            }
+            T a1[LPC], a2[LPC];
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) { a1[j] = T(0); a2[j] = T(0); }
+            const int m = len[i];
+            __builtin_amdgcn_wave_barrier();
+            ent_off[wave][lane] = lc[i];
+            ent_w[wave][lane] = we[i];
+            __builtin_amdgcn_wave_barrier();
+            constexpr int UN = 4;
+            int k = 0;
+            for (; k + UN <= m; k += UN) {
+                T x[UN][LPC];
+                P2 ww[UN];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    const int o = ent_off[wave][k + u] * CP;
+                    ww[u] = ent_w[wave][k + u];
+#pragma unroll
+                    for (int j = 0; j < LPC; ++j) x[u][j] = Xs[o + lane + 64 * j];
+                }
+#pragma unroll
+                for (int u = 0; u < UN; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPC; ++j) {
+                        a1[j] = fma(ww[u].x, x[u][j], a1[j]);
+                        a2[j] = fma(ww[u].y, x[u][j], a2[j]);
+                    }
+            }
+            for (; k < m; ++k) {
+                const int o = ent_off[wave][k] * CP;
+                const P2 ww = ent_w[wave][k];
+#pragma unroll
+                for (int j = 0; j < LPC; ++j) {
+                    const T x = Xs[o + lane + 64 * j];
+                    a1[j] = fma(ww.x, x, a1[j]);
+                    a2[j] = fma(ww.y, x, a2[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) {
+                if (MODE == 0) {
+                    q1[i][j] = a1[j];
+                    q2[i][j] = a2[j];
+                } else {
+                    const int c = c0 + lane + 64 * j;
+                    const T q = on[j] ? fma(-lm[j], a2[j], a1[j]) : T(0);
+                    if (c < p) dot[j] += (double)dv[j] * (double)q;
+                    q1[i][j] = q;
+                }
+            }
+        }
+        if (MODE == 1) {
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) red[wave * CP + lane + 64 * j] = dot[j];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // LDS done (lgkmcnt 0); vector memory untouched
+        __builtin_amdgcn_s_barrier();         // the slice is consumed and the partials written
+        __builtin_amdgcn_sched_barrier(0);
+        if (c0 + CP < p) stage(c0 + CP);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < HALO_RPW; ++i) {
+            const int64_t row = r0 + wave + HALO_WAVES * i;
+            if (row >= r1) continue;
+#pragma unroll
+            for (int j = 0; j < LPC; ++j) {
+                const int c = c0 + lane + 64 * j;
+                if (c >= p) continue;
+                if (MODE == 0) {
+                    if (Y2) {
+                        Y1[row * p + c] = q1[i][j];
+                        Y2[row * p + c] = q2[i][j];
+                    } else {
+                        Y1[row * p + c] = sel ? q2[i][j] : q1[i][j];
+                    }
+                } else {
+                    Y1[row * p + c] = q1[i][j];
+                }
+            }
+        }
+        if (MODE == 1) {
+            for (int cl = threadIdx.x; cl < CP; cl += blockDim.x) {
+                const int c = c0 + cl;
+                if (c >= p) continue;
+                double sum = 0.0;
+#pragma unroll
+                for (int k2 = 0; k2 < HALO_WAVES; ++k2) sum += red[k2 * CP + cl];
+                part[b * p + c] = sum;
+            }
+        }
+    }
+}
+
 // out[g][c] = sum of rows [g G, (g + 1) G) of an nb x p partial matrix, in row
 // order; threads run over columns, so every read is coalesced.
 __global__ __launch_bounds__(256) void k_part_rows(int64_t nb, int p, int G, const double *__restrict__ in,
@@ -865,16 +1084,26 @@ hipError_t launch_spmm_halo(hipStream_t s, int mode, int64_t nb, int p, const in
     const P2 *w = (const P2 *)wv;
     const int64_t nbp = halo_grid(nb);
     if (nbp <= 0 || nbp > 0x7fffffff) return hipErrorInvalidValue;
+    // rows of X 16-byte aligned: the DMA-staged kernel
+    const bool dma = OFKS_HALO_DMA && p % (16 / (int)sizeof(T)) == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
     if (mode == 0) {
-        hipLaunchKernelGGL((k_spmm_halo<T, 0>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff,
-                           halo, rbase, brp, lcol, w, X, Y1, Y2, sel, lam, active, part);
+        if (dma)
+            hipLaunchKernelGGL((k_spmm_halo_dma<T, 0>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0,
+                               hoff, halo, rbase, brp, lcol, w, X, Y1, Y2, sel, lam, active, part);
+        else
+            hipLaunchKernelGGL((k_spmm_halo<T, 0>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0,
+                               hoff, halo, rbase, brp, lcol, w, X, Y1, Y2, sel, lam, active, part);
         return hipGetLastError();
     }
     const int64_t ng = (nbp + HALO_G - 1) / HALO_G;
     if ((size_t)(ng + nbp) * p > part_capacity) return hipErrorInvalidValue;
     double *bpart = part + ng * p;
-    hipLaunchKernelGGL((k_spmm_halo<T, 1>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff, halo,
-                       rbase, brp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
+    if (dma)
+        hipLaunchKernelGGL((k_spmm_halo_dma<T, 1>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff,
+                           halo, rbase, brp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
+    else
+        hipLaunchKernelGGL((k_spmm_halo<T, 1>), dim3((unsigned)nbp), dim3(64 * HALO_WAVES), 0, s, nb, p, row0, hoff,
+                           halo, rbase, brp, lcol, w, X, Y1, (T *)nullptr, 0, lam, active, bpart);
     *rows_out = (int)ng;
     return hipGetLastError();
 }
