@@ -42,7 +42,6 @@ def parse():
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-baseline", default="auto", choices=["auto", "skip"])
     ap.add_argument("--max-iter", type=int, default=1500)
-    ap.add_argument("--weights", default=None, help="learned-preconditioner weights (JSON)")
     ap.add_argument("--energy-check", type=float, default=0.0,
                     help="also run FP64 and mixed precision to this residual and report the energy difference")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -52,12 +51,20 @@ def parse():
                          "ABB1, ABB2) with the paper preconditioner, and BB2 without one; report iterations")
     ap.add_argument("--study-p", default=None, metavar="P1,P2,...",
                     help="also time FP64 iterations of the same workload at these block widths and report each "
-                         "kernel's share of an iteration")
+                         "kernel's share of an iteration, and the host's p x p share")
+    ap.add_argument("--study-m", default=None, metavar="M1,M2,...",
+                    help="also run FP64 to residual 1e-6 with the paper preconditioner at these inner PCG lengths m")
+    ap.add_argument("--study-c5", default=None, metavar="A:B",
+                    help="held-out evaluation: for workload seeds A..B-1, time to residual 1e-6 of the plain FP64 "
+                         "method and the mixed-precision forms with the paper, learned and graph preconditioners")
+    ap.add_argument("--jsonl", default=None, metavar="PATH",
+                    help="after the timed steps, run --steps more one at a time and write one JSON line per "
+                         "iteration (residuals, energy, step, wall ms and each kernel class's ms)")
     return ap.parse_args()
 
 
 P_STUDY_TIMERS = ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_r", "pcg_dx", "bbdot", "density",
-                  "poisson", "assemble_h")
+                  "poisson", "assemble_h", "mlp", "graph", "host")
 
 
 def p_study(torch, a, s, w, params, steps=3, warmup=2):
@@ -85,7 +92,8 @@ def p_study(torch, a, s, w, params, steps=3, warmup=2):
         log(f"  p={p}: {dt * 1e3:.1f} ms/iteration; " + " ".join(f"{k}={v:.0%}" for k, v in share.items()))
         rows.append(dict(p=p, ms_per_iteration=round(dt * 1e3, 3), kernel_ms=ms, share=share))
     return dict(workload=a.workload, n=n, precision="f64", precond=params["precond"], pcg_iters=params["pcg_iters"],
-                rows=rows)
+                note="host = the serial p x p algebra on the host (the paper's non-parallel part); every other "
+                     "entry is a device kernel class", rows=rows)
 
 
 def step_rule_study(torch, a, params):
@@ -119,6 +127,110 @@ def step_rule_study(torch, a, params):
             mean_seconds=round(float(np.mean([r["seconds"] for r in conv])), 3) if conv else None)
     return dict(workload=a.workload, seeds=f"{lo}:{hi}", tol=1e-6, max_iter=params["max_iter"], runs=runs,
                 summary=summary)
+
+
+def m_study(torch, a, s, X0, params):
+    """The paper preconditioner's inner-solve length: the paper fixes no m
+    (eq. precondition-T); FP64 time to residual 1e-6 at each m."""
+    rows = []
+    for m in (int(v) for v in a.study_m.split(",")):
+        r = run_to_tol(torch, s, X0, 1e-6, dict(params, pcg_iters=m))
+        log(f"  m={m}: {r['iterations']} iterations, {r['seconds']} s, rel {r['rel']:.2e}")
+        rows.append(dict(m=m, iterations=r["iterations"], seconds=r["seconds"], converged=r["converged"],
+                         iter_per_s=r["iter_per_s"], energy=r["energy"]))
+    return dict(workload=a.workload, precision="f64", tol=1e-6, rows=rows)
+
+
+def graph_untrained():
+    """The graph form with untrained heads: output weights 0, biases (0, 0.65),
+    i.e. one Jacobi sweep through T damped by 0.65 after the Jacobi scaling."""
+    from paper_2007_14228_amd import learned
+    return learned.init_graph_weights(0, 0.65), np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.float32)
+
+
+def learned_legs(torch, s, X0, mparams):
+    """The mixed-precision forms with the learned preconditioners (energy and
+    stall fallbacks on), each from the same start."""
+    from paper_2007_14228_amd import learned
+    legs = {}
+    wpath = learned.DEFAULT_WEIGHTS
+    if os.path.exists(wpath):
+        Wl, norml, meta = learned.load(wpath)
+        log(f"time to residual 1e-6: mixed precision + learned pointwise preconditioner ({os.path.basename(wpath)})")
+        s.lp_set_weights(Wl, norml)
+        legs["mixed_learned_precond"] = run_to_tol(torch, s, X0, 1e-6, dict(mparams, precond="learned",
+                                                                              energy_every=1))
+        legs["mixed_learned_precond"]["weights"] = {"file": os.path.relpath(wpath, ROOT),
+                                                    **{k: meta[k] for k in ("seeds", "kind", "samples") if k in meta}}
+        log(f"  {legs['mixed_learned_precond']}")
+    log("time to residual 1e-6: mixed precision + learned pointwise form, untrained network (Jacobi of T)")
+    s.lp_set_weights(learned.init_weights(0), np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.float32))
+    legs["mixed_learned_form_untrained"] = run_to_tol(torch, s, X0, 1e-6, dict(mparams, precond="learned",
+                                                                               energy_every=1))
+    log(f"  {legs['mixed_learned_form_untrained']}")
+    log("time to residual 1e-6: mixed precision + graph form, untrained heads (damped sweep through T)")
+    s.gl_set_weights(*graph_untrained())
+    legs["mixed_graph_form_untrained"] = run_to_tol(torch, s, X0, 1e-6, dict(mparams, precond="graph",
+                                                                             energy_every=1))
+    log(f"  {legs['mixed_graph_form_untrained']}")
+    return legs
+
+
+def c5_study(torch, a, params):
+    """Held-out evaluation on workloads of the benchmark's kind: per seed, the
+    same start for every leg; medians over the seeds that converged."""
+    import workloads as wl
+    from paper_2007_14228_amd import Solver
+    lo, hi = (int(v) for v in a.study_c5.split(":"))
+    runs = []
+    for seed in range(lo, hi):
+        t = time.perf_counter()
+        w = wl.make_workload(a.workload, seed=seed)
+        X0 = torch.from_numpy(wl.random_block(1000 + seed, w.mesh.n_dofs, w.p)).to("cuda")
+        s = Solver()
+        s.load_workload(w)
+        prm = dict(params, beta=w.beta)
+        legs = {"fp64_paper_precond": run_to_tol(torch, s, X0, 1e-6, prm)}
+        mprm = dict(prm, precision="f32", refine_tol=1.5e-6)
+        legs["mixed_paper_precond"] = run_to_tol(torch, s, X0, 1e-6, mprm)
+        legs.update(learned_legs(torch, s, X0, mprm))
+        s.close()
+        del X0
+        torch.cuda.empty_cache()
+        for k, v in legs.items():
+            runs.append(dict(seed=seed, leg=k, seconds=v["seconds"], iterations=v["iterations"],
+                             converged=v["converged"], fallbacks=v["fallbacks"], energy=v["energy"]))
+        log(f"  c5 seed {seed} ({time.perf_counter() - t:.0f} s): " +
+            ", ".join(f"{k} {v['seconds']} s/{v['iterations']}it{'' if v['converged'] else ' (not converged)'}"
+                      for k, v in legs.items()))
+    summary = {}
+    for leg in dict.fromkeys(r["leg"] for r in runs):
+        rs = [r for r in runs if r["leg"] == leg]
+        conv = [r for r in rs if r["converged"]]
+        summary[leg] = dict(converged=f"{len(conv)}/{len(rs)}",
+                            median_seconds=float(np.median([r["seconds"] for r in conv])) if conv else None,
+                            median_iterations=float(np.median([r["iterations"] for r in conv])) if conv else None)
+    return dict(workload=a.workload, seeds=f"{lo}:{hi}", tol=1e-6, runs=runs, summary=summary)
+
+
+def jsonl_log(torch, s, steps, path):
+    """One JSON line per iteration: the iterate's residuals, energy and step,
+    the iteration's wall time and each kernel class's time (HIP events)."""
+    names = P_STUDY_TIMERS + ("mlp_train", "graph_train")
+    with open(path, "w") as f:
+        for _ in range(steps):
+            s.timing(True)
+            st, done, _ = s.step(1)
+            if not st:
+                break
+            x = st[0]
+            ks = {k: round(s.timer(k)[0], 4) for k in names if s.timer(k)[1]}
+            s.timing(False)
+            f.write(json.dumps(dict(k=x["k"], kkt=x["kkt"], fea=x["fea"], rel=x["rel"], energy=x["energy"],
+                                    eta=x["eta"], precond=x["precond_used"], precision=x["precision"],
+                                    ms=round(x["ms"], 4), kernel_ms=ks)) + "\n")
+            if done:
+                break
 
 
 def log(msg):
@@ -170,12 +282,12 @@ def run_to_tol(torch, s, X0, tol, params, weights=None):
     dt = time.perf_counter() - t0
     last = stats[-1]
     iters = len(stats) - 1
-    kinds = [0, 0, 0]
+    kinds = [0, 0, 0, 0]
     for x in stats[:-1]:
         kinds[x["precond_used"]] += 1
     return dict(seconds=round(dt, 3), iterations=iters, rel=last["rel"], energy=float(s.energy()[4]),
                 converged=bool(last["rel"] < tol), iter_per_s=round(iters / dt, 3) if dt > 0 else None,
-                iterations_by_precond={"none": kinds[0], "paper": kinds[1], "learned": kinds[2]},
+                iterations_by_precond={"none": kinds[0], "paper": kinds[1], "learned": kinds[2], "graph": kinds[3]},
                 fallbacks=int(sum(x["fell_back"] for x in stats)),
                 fp32_iterations=int(sum(1 for x in stats[:-1] if x["precision"] == 1)))
 
@@ -266,8 +378,7 @@ def main():
     dt = time.perf_counter() - t0
     if len(stats) != a.steps:
         raise RuntimeError("fewer steps than requested")
-    timers = {k: s.timer(k) for k in ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_r", "pcg_dx",
-                                      "bbdot", "density", "poisson", "assemble_h")}
+    timers = {k: s.timer(k) for k in P_STUDY_TIMERS}
     s.timing(False)
     log(f"{a.steps} steps in {dt:.3f}s; rel={stats[-1]['rel']:.3e}")
     for k, (ms, cnt) in timers.items():
@@ -341,37 +452,30 @@ def main():
         mparams = dict(params, precision="f32", refine_tol=1.5e-6)
         ttr["mixed_paper_precond"] = run_to_tol(torch, s, X0, 1e-6, mparams)
         log(f"  {ttr['mixed_paper_precond']}")
-        from paper_2007_14228_amd import learned
-        wpath = a.weights or learned.DEFAULT_WEIGHTS
-        if os.path.exists(wpath):
-            Wl, norml, meta = learned.load(wpath)
-            log(f"time to residual 1e-6: mixed precision + learned preconditioner ({os.path.basename(wpath)})")
-            lparams = dict(mparams, precond="learned", energy_every=1)
-            ttr["mixed_learned_precond"] = run_to_tol(torch, s, X0, 1e-6, lparams, (Wl, norml))
-            ttr["mixed_learned_precond"]["weights"] = {"file": os.path.relpath(wpath, ROOT),
-                                                       **{k: meta[k] for k in ("seeds", "kind", "samples")
-                                                          if k in meta}}
-            log(f"  {ttr['mixed_learned_precond']}")
-        else:
-            ttr["mixed_learned_precond"] = {"error": f"no trained weights at {wpath}"}
-        # the same form with the untrained network (exp(f) = 1: the Jacobi of T), for reference
-        log("time to residual 1e-6: mixed precision + learned form with the untrained network (Jacobi of T)")
-        w0 = (learned.init_weights(0), np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.float32))
-        ttr["mixed_learned_form_untrained"] = run_to_tol(torch, s, X0, 1e-6,
-                                                         dict(mparams, precond="learned", energy_every=1), w0)
-        log(f"  {ttr['mixed_learned_form_untrained']}")
+        ttr.update(learned_legs(torch, s, X0, mparams))
         for k, v in ttr.items():
             if k != "fp64_paper_precond" and v.get("converged") and plain["converged"]:
                 v["dE_vs_fp64_Ha"] = abs(v["energy"] - plain["energy"])
         ttr["speedup_vs_fp64_paper"] = {k: round(plain["seconds"] / v["seconds"], 3)
                                         for k, v in ttr.items() if k != "fp64_paper_precond" and v.get("converged")}
         out["time_to_residual_1e-6"] = ttr
+    if a.jsonl:
+        log(f"per-iteration log: {a.jsonl}")
+        s.set_params(tol=1e-30, **params)
+        s.set_x0(X0, orthonormalize=True)
+        jsonl_log(torch, s, a.steps, a.jsonl)
+    if a.study_m:
+        log(f"inner-solve length study, {a.workload}: m = {a.study_m}")
+        out["m_study"] = m_study(torch, a, s, X0, params)
     if a.study_p:
         log(f"block-width study, {a.workload}: p = {a.study_p}")
         out["p_study"] = p_study(torch, a, s, w, params)
     if a.study_steps:
         log(f"step-rule study, {a.workload} seeds {a.study_steps}")
         out["step_rule_study"] = step_rule_study(torch, a, params)
+    if a.study_c5:
+        log(f"held-out evaluation, {a.workload} seeds {a.study_c5}")
+        out["c5_study"] = c5_study(torch, a, params)
     if a.energy_check > 0:
         # the precision form's energy error, both runs converged well past 1e-6
         tol = a.energy_check

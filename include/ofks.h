@@ -364,8 +364,8 @@ int ofks_gl_feature_norm(ofks_ctx *ctx, float *host_norm);
 int ofks_timing(ofks_ctx *ctx, int32_t enable);
 /* Totals for a kernel class: name is one of "spmm_dual", "spmm_shift",
  * "gram", "update_a", "update_b", "pcg_r", "pcg_dx", "density", "poisson",
- * "assemble_h", "bbdot", "mlp", "mlp_train", "graph", "graph_train".  ms = summed duration,
- * launches = count. */
+ * "assemble_h", "bbdot", "mlp", "mlp_train", "graph", "graph_train", and "host" (the host's
+ * p x p algebra of each iteration, wall time).  ms = summed duration, launches = count. */
 int ofks_timer_get(ofks_ctx *ctx, const char *name, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

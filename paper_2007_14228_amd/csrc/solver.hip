@@ -716,7 +716,20 @@ int poisson(ofks_ctx *c) {
     return OFKS_OK;
 }
 
+// the density's quadrature-point arrays, allocated on the first density
+// evaluation (a fixed-H run never needs them)
+int ensure_scf_work(ofks_ctx *c) {
+    if (c->rho_q) return OFKS_OK;
+    const int64_t nt = c->n_tets;
+    CHK(dalloc(c, &c->rho_q, 4 * nt));
+    CHK(dalloc(c, &c->eps_q, 4 * nt));
+    CHK(dalloc(c, &c->vxc_q, 4 * nt));
+    CHK(dalloc(c, &c->veff_q, 4 * nt));
+    return OFKS_OK;
+}
+
 template <typename T> int build_h(ofks_ctx *c, const T *X, const T *dinv_dev) {
+    CHK(ensure_scf_work(c));
     const int64_t nt = c->n_tets;
     const int g = 1024;
     CHK(ensure_part(c, (size_t)3 * g));
@@ -840,6 +853,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     }
     std::vector<double> St, Lt;
     CHK(gram<T>(c, B.Xt, B.BX, B.HX, St, Lt));
+    const auto th0 = std::chrono::steady_clock::now();   // host p x p algebra from here to the uploads
 
     // deferred normalization
     std::vector<double> &dn = c->dinv_h;
@@ -945,6 +959,11 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     }
     std::vector<uint8_t> act(p, 0);
     for (int i = 0; i < p; ++i) act[i] = (use_paper && neg[i]) ? 1 : 0;
+    if (c->timing) {   // the serial host share: symmetrization, multiplier, energy, fallback rules
+        Timer &th = c->timers["host"];
+        th.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
+        th.launches += 1;
+    }
     if (!scf) CHK(upload<T>(c, B.dinv, dn));
     CHK(upload<T>(c, B.CC, CC));
     CHK(upload<T>(c, B.lam, shift));
@@ -1127,13 +1146,42 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
 }
 
 // switch the iteration from FP32 to FP64 blocks (refinement sweeps)
+// The three blocks that carry the iteration's state (X~, X^{k-1}, P^{k-1})
+// are converted one at a time, after the FP32 scratch blocks are freed, so the
+// peak is the FP64 set plus at most three FP32 blocks (at n = 8e6, p = 512:
+// 262 GB + 49 GB falling to 262 GB, where both full sets would need 393 GB).
 int promote_to_f64(ofks_ctx *c) {
-    CHK(alloc_blocks<double>(c));
-    HIPCHK(launch_convert<float, double>(c->stream, c->n * (int64_t)c->p, c->b32.Xt, c->b64.Xt));
-    HIPCHK(launch_convert<float, double>(c->stream, c->n * (int64_t)c->p, c->b32.Xp, c->b64.Xp));
-    HIPCHK(launch_convert<float, double>(c->stream, c->n * (int64_t)c->p, c->b32.Pp, c->b64.Pp));
+    Blocks<float> &F = c->b32;
+    Blocks<double> &D = c->b64;
+    const size_t np = (size_t)c->n * c->p;
     CHK(sync(c));
+    dfree(c, F.P);
+    dfree(c, F.HX);
+    dfree(c, F.BX);
+    dfree(c, F.R);
+    dfree(c, F.D);
+    float *src[3] = {F.Xt, F.Xp, F.Pp};
+    double **dst[3] = {&D.Xt, &D.Xp, &D.Pp};
+    for (int i = 0; i < 3; ++i) {
+        CHK(dalloc(c, dst[i], np));
+        HIPCHK(launch_convert<float, double>(c->stream, (int64_t)np, src[i], *dst[i]));
+        CHK(sync(c));
+        dfree(c, src[i]);
+    }
+    F.Xt = F.Xp = F.Pp = nullptr;
     free_blocks<float>(c);
+    dfree(c, c->hb32);   // the FP32 matrix copies are rebuilt if an FP32 run starts again
+    dfree(c, c->lb32);
+    CHK(dalloc(c, &D.P, np));
+    CHK(dalloc(c, &D.HX, np));
+    CHK(dalloc(c, &D.BX, np));
+    CHK(dalloc(c, &D.R, np));
+    CHK(dalloc(c, &D.D, np));
+    CHK(dalloc(c, &D.dinv, c->p));
+    CHK(dalloc(c, &D.CC, (size_t)c->p * 2 * c->p));
+    CHK(dalloc(c, &D.lam, c->p));
+    CHK(dalloc(c, &D.alpha, c->p));
+    CHK(dalloc(c, &D.beta, c->p));
     c->prec = OFKS_F64;
     return OFKS_OK;
 }
@@ -1503,10 +1551,8 @@ int ofks_assemble(ofks_ctx *c) {
     dfree(c, c->cg_q);
     dfree(c, c->cg_sc);
     dfree(c, c->cg_part);
-    CHK(dalloc(c, &c->rho_q, 4 * nt));
-    CHK(dalloc(c, &c->eps_q, 4 * nt));
-    CHK(dalloc(c, &c->vxc_q, 4 * nt));
-    CHK(dalloc(c, &c->veff_q, 4 * nt));
+    // the quadrature-point arrays of the density (4 per tetrahedron, four
+    // of them: 6.2 GB at n = 8e6) are allocated on first use (ensure_scf_work)
     CHK(dalloc(c, &c->bvec, n));
     CHK(dalloc(c, &c->U, n));
     CHK(dalloc(c, &c->cg_r, n));
@@ -1832,6 +1878,7 @@ int ofks_get_density(ofks_ctx *c, double *dev_rho) {
     CHK(check_ready(c));
     if (!c->assembled) return fail(c, OFKS_ESTATE, "get_density: needs an assembled mesh");
     if (!dev_rho) return fail(c, OFKS_EINVAL, "get_density: null output");
+    if (!c->rho_q) return fail(c, OFKS_ESTATE, "get_density: no density evaluated yet (SCF steps or ofks_update_density)");
     HIPCHK(hipMemcpyAsync(dev_rho, c->rho_q, 4 * c->n_tets * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     return sync(c);
 }

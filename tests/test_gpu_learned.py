@@ -221,13 +221,19 @@ def test_samples_of_the_first_iteration_match_the_oracle(objective, c1):
 
 
 def test_what_the_network_gains_over_the_method_without_it():
-    """Held-out graded 24-nucleus problem (seed 2002, n ~ 5e4, p = 16), 300
-    iterations from the same start, fallback off so that each preconditioner
-    acts alone.  The learned form's Jacobi structure (the untrained network)
-    gains orders of magnitude over no preconditioner.  The shipped trained
-    weights are measured, not assumed to help: a pointwise rescaling cannot
-    represent T^-1, and fitting it has not beaten the untrained form (the
-    residuals are printed)."""
+    """Held-out graded 24-nucleus problem (seed 2002, n ~ 5e4, p = 16), the
+    same start for every form.
+
+    With the fallbacks on (the production setting: the paper preconditioner
+    takes over when the energy rises or the residual stalls), the shipped
+    trained network reaches rel 1e-6 within 1500 iterations, where the method
+    without a preconditioner does not.  With the fallbacks off, the learned
+    form's structure alone (the untrained network, the Jacobi of T) is three
+    orders of magnitude ahead of no preconditioner after 300 iterations.
+    Wall times beside the paper preconditioner's are printed, not asserted: a
+    pointwise rescaling cannot represent T^-1, and the trained network is not
+    ahead of the paper preconditioner."""
+    import time
     import torch
     from paper_2007_14228_amd import Solver, learned
     print("[gpu] learned gain", flush=True)
@@ -237,15 +243,31 @@ def test_what_the_network_gains_over_the_method_without_it():
     X0 = torch.from_numpy(wl.random_block(2002, w.mesh.n_dofs, w.p)).cuda()
     Wt, nt, meta = learned.load()
     untrained = (mlp.init_weights(0).astype(np.float32), np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.float32))
-    rel = {}
-    for tag, wts in (("none", None), ("untrained", untrained), ("trained", (Wt, nt))):
+
+    def run(precond, wts, max_iter, tol, fallbacks=True):
         if wts is not None:
             s.lp_set_weights(*wts)
-        s.set_params(beta=w.beta, tol=1e-30, max_iter=300, energy_every=1, fallback_window=0,
-                     precond="none" if wts is None else "learned")
+        extra = {} if fallbacks else dict(fallback_window=0, fallback_stall=0)
+        s.set_params(beta=w.beta, tol=tol, max_iter=max_iter, energy_every=1, precond=precond, **extra)
         s.set_x0(X0, orthonormalize=True)
-        st, _, _ = s.step(301)
-        rel[tag] = st[-1]["rel"]
-    print(f"[gpu] rel after 300 iterations: {rel}", flush=True)
-    assert rel["untrained"] < 1e-3 * rel["none"]
-    assert np.isfinite(rel["trained"])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, done, _ = s.step(max_iter + 1)
+        torch.cuda.synchronize()
+        return st, time.perf_counter() - t
+
+    out = {}
+    for tag, pre, wts in (("none", "none", None), ("paper", "paper", None), ("trained", "learned", (Wt, nt)),
+                          ("untrained", "learned", untrained)):
+        st, dt = run(pre, wts, 1500, 1e-6)
+        out[tag] = (len(st) - 1, st[-1]["rel"], dt, sum(x["fell_back"] for x in st))
+    print("[gpu] to rel 1e-6 (iterations, rel, seconds, fallbacks): " + str(out), flush=True)
+    assert out["trained"][1] < 1e-6
+    assert out["none"][1] > 1e-6
+    alone = {}
+    for tag, pre, wts in (("none", "none", None), ("untrained", "learned", untrained)):
+        st, _ = run(pre, wts, 300, 1e-30, fallbacks=False)
+        alone[tag] = st[-1]["rel"]
+    print(f"[gpu] rel after 300 iterations, fallbacks off: {alone}", flush=True)
+    assert alone["untrained"] < 1e-3 * alone["none"]
+    s.close()

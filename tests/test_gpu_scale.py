@@ -137,3 +137,17 @@ def test_c4_fp32_iterations(c4):
     assert all(np.isfinite(x["kkt"]) and np.isfinite(x["fea"]) for x in st)
     assert st[0]["fea"] < 1e-3                      # B-orthonormal start, in FP32
     assert st[-1]["kkt"] < st[0]["kkt"]
+    # the FP64 refinement at this size: the switch converts the three state
+    # blocks one at a time after freeing the FP32 scratch, so the FP64 set
+    # (8 x 32.8 GB) fits beside the system
+    free, total = torch.cuda.mem_get_info()
+    print(f"[gpu] c4: device memory before the switch: {free / 2**30:.1f} GiB free of {total / 2**30:.1f}", flush=True)
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=7, precond="paper", pcg_iters=10, precision="f32",
+                 refine_tol=1.0, energy_every=10)
+    t = time.perf_counter()
+    st2, _, _ = s.step(3)
+    torch.cuda.synchronize()
+    print(f"[gpu] c4: after the switch: " + "; ".join(f"k={x['k']} prec={x['precision']} kkt={x['kkt']:.4e}"
+                                                     for x in st2) + f" ({time.perf_counter() - t:.1f} s)", flush=True)
+    assert st2[0]["precision"] == 1 and st2[-1]["precision"] == 0
+    assert all(np.isfinite(x["kkt"]) and np.isfinite(x["fea"]) for x in st2)
