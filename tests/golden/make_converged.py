@@ -13,7 +13,9 @@ linear: a held-out 24-nucleus cluster (seed 2002) at n ~ 5e4, p = 16, fixed
   scipy), independent of the PCAL iteration.  The oracle's PCAL is then run
   to a relative residual of 1e-9 and must reach them.
 scf: a 4-nucleus cluster of the SCF kind (seed 0) at n ~ 5e4, the full
-  Kohn-Sham LDA problem.  The oracle's PCAL is run to 1e-9; at the fixed point
+  Kohn-Sham LDA problem.  The oracle's PCAL is run to 1e-11 (at 1e-9 the
+  remaining infeasibility X^T B X - I ~ 1e-8 still moves the energy of the
+  iterate by a few 1e-8 Ha, to first order); at the fixed point
   the occupied subspace must be the lowest p eigenvectors of its own H(X)
   (aufbau), which is checked by a shift-invert solve on H(X) before the
   energy is stored.
@@ -34,6 +36,7 @@ from oracle import fem, pcal, scf  # noqa: E402
 
 LINEAR = dict(kind="c3", seed=2002, target_dofs=50_000, p=16)
 SCF = dict(kind="c2", seed=0, target_dofs=50_000)
+SCF_TOL = 1e-11
 
 
 def lowest_eigs(A, B, k, sigma):
@@ -90,11 +93,11 @@ def scf_case():
             last[0] = time.time()
             print(f"scf: iteration {k} ({time.time() - t:.0f} s)", flush=True)
 
-    X, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-9, max_iter=5000, precond="paper",
+    X, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=SCF_TOL, max_iter=5000, precond="paper",
                                               pcg_iters=10), callback=progress)
     print(f"scf: n={d.n} p={p} oracle PCAL {len(hist) - 1} iterations ({time.time() - t:.0f} s), "
           f"rel {hist[-1].rel:.2e}, E {hist[-1].energy:.12f}", flush=True)
-    assert hist[-1].rel < 1e-9
+    assert hist[-1].rel < SCF_TOL
     # aufbau at the fixed point: the Ritz values of H(X) on span(X) are its p lowest eigenvalues
     prob.set_x(X)
     Hx = d.csr(prob.Hval)
@@ -106,9 +109,9 @@ def scf_case():
     E = prob.energy_direct(X)
     out = dict(recipe=cfg, workload=wl.CONFIGS["c2"] + f" (n ~ {cfg['target_dofs']})", n=d.n, nnz=d.nnz, p=p,
                beta=w.beta, occupation=2.0, Z=[float(z) for z in w.Z], start_seed=1000 + cfg["seed"],
-               energy=float(hist[-1].energy), energy_direct=E, iterations=len(hist) - 1, tol=1e-9,
+               energy=float(hist[-1].energy), energy_direct=E, iterations=len(hist) - 1, tol=SCF_TOL,
                ritz_values=[float(x) for x in lam], eigenvalues_of_H=[float(x) for x in ev],
-               source="oracle SCF PCAL (paper preconditioner, BB2) to rel 1e-9; fixed point checked by the aufbau "
+               source="oracle SCF PCAL (paper preconditioner, BB2) to rel 1e-11; fixed point checked by the aufbau "
                       "property with scipy.sparse.linalg.eigsh on H(X)")
     with open(os.path.join(HERE, "converged_scf_c2type.json"), "w") as f:
         json.dump(out, f, indent=1)
