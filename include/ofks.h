@@ -148,10 +148,29 @@ int ofks_csr_load(ofks_ctx *ctx, int64_t n, int64_t nnz, const int64_t *row_ptr,
 
 int ofks_set_params(ofks_ctx *ctx, const ofks_params *params);
 
+/* Caller-owned workspace for the iteration's device state: the blocks of
+ * width p and their per-column arrays, the per-block partial sums, the graph
+ * form's smoothing weights, an FP32 run's FP32 copies of H and L/2 and the
+ * FP64 set its refinement switches to, and the SCF density's quadrature
+ * arrays.  ofks_workspace_size gives the bytes that width p and the given
+ * parameters need on the current system.  After ofks_set_workspace(dev_ws,
+ * bytes) (device memory, 256-byte aligned, owned by the caller and valid
+ * until the context is destroyed or another workspace is set),
+ * ofks_set_x0, ofks_state_set and ofks_step take that state from it and call
+ * no hipMalloc.  The assembled system (CSR, values, halo plan, mesh arrays)
+ * stays library-owned; the single-kernel, training, data-collection and
+ * post-processing calls may still allocate.  Setting a workspace releases
+ * the current iterate (ofks_set_x0 or ofks_state_set must follow);
+ * dev_ws = NULL returns to library allocation.  ECAPACITY when the state
+ * outgrows the workspace (other parameters than those it was sized for). */
+int ofks_workspace_size(ofks_ctx *ctx, int32_t p, const ofks_params *params, size_t *bytes);
+int ofks_set_workspace(ofks_ctx *ctx, void *dev_ws, size_t bytes);
+
 /* Starting block X0 (device f64[n*p]).  b_orthonormalize = 1 applies the
  * Cholesky-based Gram-Schmidt of Section 4.2 (X0 = V R^{-1}, R^T R = V^T B V);
  * 0 takes X0 as given.  Allocates the iteration blocks for this p.  Resets
- * the iteration counter.  ENOTSPD if V^T B V is not positive definite;
+ * the iteration counter, the fallback history and the Hartree solve's warm
+ * start, so the run depends only on X0 and the parameters.  ENOTSPD if V^T B V is not positive definite;
  * EZERONORM if a column taken as given has zero B-norm. */
 int ofks_set_x0(ofks_ctx *ctx, int32_t p, const double *dev_X0, int32_t b_orthonormalize);
 

@@ -75,6 +75,8 @@ SIGNATURES = [
     ("ofks_csr_get", I32, [P, P, P, P, P, P]),
     ("ofks_csr_load", I32, [P, I64, I64, P, P, P, P, P]),
     ("ofks_set_params", I32, [P, ctypes.POINTER(Params)]),
+    ("ofks_workspace_size", I32, [P, I32, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+    ("ofks_set_workspace", I32, [P, P, ctypes.c_size_t]),
     ("ofks_set_x0", I32, [P, I32, P, I32]),
     ("ofks_step", I32, [P, I32, ctypes.POINTER(IterStats), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     ("ofks_residual", I32, [P, ctypes.POINTER(_c_double), ctypes.POINTER(_c_double), ctypes.POINTER(_c_double)]),

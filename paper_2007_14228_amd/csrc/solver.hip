@@ -299,6 +299,12 @@ struct ofks_ctx {
     size_t lp_u_bytes = 0;
 
     double *scratch_dev = nullptr;   // this device's copy of `scratch` (ofks_gram_noalloc)
+    // caller-owned workspace (ofks_set_workspace): the iteration's device
+    // state is carved from it in order while ws_carve is set
+    char *ws_base = nullptr;
+    size_t ws_size = 0, ws_off = 0;
+    size_t ws_f64_base = 0, ws_f64_cap = 0;   // where the FP64 set of an FP32 run's refinement goes
+    bool ws_carve = false;
     // graph learned preconditioner
     float *gl_W = nullptr, *gl_norm = nullptr;   // 226 weights, 8 standardization constants (device)
     bool gl_ready = false;
@@ -358,8 +364,38 @@ template <typename T> int dalloc(ofks_ctx *c, T **out, size_t count) {
     return OFKS_OK;
 }
 
+// Iteration-state allocation: carved from the caller's workspace while one
+// is set and ws_carve is on (the entry points that build or advance the
+// iteration), else hipMalloc.  Pieces are 256-byte aligned.
+template <typename T> int walloc(ofks_ctx *c, T **out, size_t count) {
+    if (!(c->ws_base && c->ws_carve)) return dalloc(c, out, count);
+    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~size_t(255);
+    if (c->ws_off + bytes > c->ws_size)
+        return fail(c, OFKS_ECAPACITY, "workspace exhausted: %zu of %zu bytes used, %zu more needed (see ofks_workspace_size)",
+                    c->ws_off, c->ws_size, bytes);
+    *out = (T *)(c->ws_base + c->ws_off);
+    c->ws_off += bytes;
+    return OFKS_OK;
+}
+
+// bytes that walloc takes for a set of nblk blocks of n x p elements of
+// `elem` bytes and their five per-column arrays (alloc_blocks' layout)
+size_t ws_piece(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) & ~size_t(255); }
+size_t ws_block_set(size_t n, size_t p, size_t elem, int nblk) {
+    return nblk * ws_piece(n * p * elem) + 3 * ws_piece(p * elem) + ws_piece(2 * p * p * elem) + ws_piece(p * elem);
+}
+// the region an FP32 run keeps for FP64 blocks: the start block's setup and,
+// when a refinement may follow, the whole FP64 set that replaces the FP32 one
+size_t ws_f64_region(ofks_ctx *c, int p) {
+    return ws_block_set(c->n, p, sizeof(double), c->prm.refine_tol > 0.0 ? 8 : 3);
+}
+
 template <typename T> void dfree(ofks_ctx *c, T *&ptr) {
     if (!ptr) return;
+    if (c->ws_base && (const char *)ptr >= c->ws_base && (const char *)ptr < c->ws_base + c->ws_size) {
+        ptr = nullptr;   // workspace memory is the caller's
+        return;
+    }
     auto it = std::find(c->allocs.begin(), c->allocs.end(), (void *)ptr);
     if (it != c->allocs.end()) c->allocs.erase(it);
     (void)hipFree((void *)ptr);
@@ -387,7 +423,8 @@ int ensure_part(ofks_ctx *c, size_t doubles) {
     if (c->part_cap >= doubles) return OFKS_OK;
     HIPCHK(hipStreamSynchronize(c->stream));   // kernels in flight may still use the old buffer
     dfree(c, c->part);
-    CHK(dalloc(c, &c->part, doubles));
+    c->part_cap = 0;
+    CHK(walloc(c, &c->part, doubles));
     c->part_cap = doubles;
     return OFKS_OK;
 }
@@ -461,21 +498,21 @@ template <> const void *lbT<float>(ofks_ctx *c) { return c->lb32; }
 template <typename T> int alloc_blocks(ofks_ctx *c, bool setup_only = false) {
     Blocks<T> &b = blk<T>(c);
     const size_t np = (size_t)c->n * c->p;
-    CHK(dalloc(c, &b.Xt, np));
-    CHK(dalloc(c, &b.HX, np));
-    CHK(dalloc(c, &b.BX, np));
+    CHK(walloc(c, &b.Xt, np));
+    CHK(walloc(c, &b.HX, np));
+    CHK(walloc(c, &b.BX, np));
     if (!setup_only) {
-        CHK(dalloc(c, &b.Xp, np));
-        CHK(dalloc(c, &b.P, np));
-        CHK(dalloc(c, &b.Pp, np));
-        CHK(dalloc(c, &b.R, np));
-        CHK(dalloc(c, &b.D, np));
+        CHK(walloc(c, &b.Xp, np));
+        CHK(walloc(c, &b.P, np));
+        CHK(walloc(c, &b.Pp, np));
+        CHK(walloc(c, &b.R, np));
+        CHK(walloc(c, &b.D, np));
     }
-    CHK(dalloc(c, &b.dinv, c->p));
-    CHK(dalloc(c, &b.CC, (size_t)c->p * 2 * c->p));
-    CHK(dalloc(c, &b.lam, c->p));
-    CHK(dalloc(c, &b.alpha, c->p));
-    CHK(dalloc(c, &b.beta, c->p));
+    CHK(walloc(c, &b.dinv, c->p));
+    CHK(walloc(c, &b.CC, (size_t)c->p * 2 * c->p));
+    CHK(walloc(c, &b.lam, c->p));
+    CHK(walloc(c, &b.alpha, c->p));
+    CHK(walloc(c, &b.beta, c->p));
     return OFKS_OK;
 }
 
@@ -718,14 +755,23 @@ int poisson(ofks_ctx *c) {
 
 // the density's quadrature-point arrays, allocated on the first density
 // evaluation (a fixed-H run never needs them)
+void free_scf_work(ofks_ctx *c) {
+    dfree(c, c->rho_q);
+    dfree(c, c->eps_q);
+    dfree(c, c->vxc_q);
+    dfree(c, c->veff_q);
+}
+
 int ensure_scf_work(ofks_ctx *c) {
-    if (c->rho_q) return OFKS_OK;
+    if (c->rho_q && c->eps_q && c->vxc_q && c->veff_q) return OFKS_OK;
+    free_scf_work(c);   // all four or none
     const int64_t nt = c->n_tets;
-    CHK(dalloc(c, &c->rho_q, 4 * nt));
-    CHK(dalloc(c, &c->eps_q, 4 * nt));
-    CHK(dalloc(c, &c->vxc_q, 4 * nt));
-    CHK(dalloc(c, &c->veff_q, 4 * nt));
-    return OFKS_OK;
+    int rc = walloc(c, &c->rho_q, 4 * nt);
+    if (rc == OFKS_OK) rc = walloc(c, &c->eps_q, 4 * nt);
+    if (rc == OFKS_OK) rc = walloc(c, &c->vxc_q, 4 * nt);
+    if (rc == OFKS_OK) rc = walloc(c, &c->veff_q, 4 * nt);
+    if (rc != OFKS_OK) free_scf_work(c);
+    return rc;
 }
 
 template <typename T> int build_h(ofks_ctx *c, const T *X, const T *dinv_dev) {
@@ -813,7 +859,8 @@ int ensure_gl_ft(ofks_ctx *c, size_t count) {
     if (c->gl_ft_cap >= count) return OFKS_OK;
     if (c->gl_ft) CHK(sync(c));   // queued work may still read the old buffer
     dfree(c, c->gl_ft);
-    CHK(dalloc(c, &c->gl_ft, count));
+    c->gl_ft_cap = 0;
+    CHK(walloc(c, &c->gl_ft, count));
     c->gl_ft_cap = count;
     return OFKS_OK;
 }
@@ -1150,20 +1197,26 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
 // are converted one at a time, after the FP32 scratch blocks are freed, so the
 // peak is the FP64 set plus at most three FP32 blocks (at n = 8e6, p = 512:
 // 262 GB + 49 GB falling to 262 GB, where both full sets would need 393 GB).
-int promote_to_f64(ofks_ctx *c) {
+int promote_to_f64_impl(ofks_ctx *c) {
     Blocks<float> &F = c->b32;
     Blocks<double> &D = c->b64;
     const size_t np = (size_t)c->n * c->p;
+    if (c->ws_base && c->ws_carve && ws_block_set(c->n, c->p, sizeof(double), 8) > c->ws_f64_cap)
+        return fail(c, OFKS_ECAPACITY, "workspace: no room kept for the FP64 blocks (sized with refine_tol = 0)");
     CHK(sync(c));
     dfree(c, F.P);
     dfree(c, F.HX);
     dfree(c, F.BX);
     dfree(c, F.R);
     dfree(c, F.D);
+    // with a workspace the FP64 set goes to the region set_x0 / state_set
+    // kept for it (the start block's setup blocks there are dead)
+    const size_t ws_hi = c->ws_off;
+    if (c->ws_base && c->ws_carve) c->ws_off = c->ws_f64_base;
     float *src[3] = {F.Xt, F.Xp, F.Pp};
     double **dst[3] = {&D.Xt, &D.Xp, &D.Pp};
     for (int i = 0; i < 3; ++i) {
-        CHK(dalloc(c, dst[i], np));
+        CHK(walloc(c, dst[i], np));
         HIPCHK(launch_convert<float, double>(c->stream, (int64_t)np, src[i], *dst[i]));
         CHK(sync(c));
         dfree(c, src[i]);
@@ -1172,18 +1225,60 @@ int promote_to_f64(ofks_ctx *c) {
     free_blocks<float>(c);
     dfree(c, c->hb32);   // the FP32 matrix copies are rebuilt if an FP32 run starts again
     dfree(c, c->lb32);
-    CHK(dalloc(c, &D.P, np));
-    CHK(dalloc(c, &D.HX, np));
-    CHK(dalloc(c, &D.BX, np));
-    CHK(dalloc(c, &D.R, np));
-    CHK(dalloc(c, &D.D, np));
-    CHK(dalloc(c, &D.dinv, c->p));
-    CHK(dalloc(c, &D.CC, (size_t)c->p * 2 * c->p));
-    CHK(dalloc(c, &D.lam, c->p));
-    CHK(dalloc(c, &D.alpha, c->p));
-    CHK(dalloc(c, &D.beta, c->p));
+    CHK(walloc(c, &D.P, np));
+    CHK(walloc(c, &D.HX, np));
+    CHK(walloc(c, &D.BX, np));
+    CHK(walloc(c, &D.R, np));
+    CHK(walloc(c, &D.D, np));
+    CHK(walloc(c, &D.dinv, c->p));
+    CHK(walloc(c, &D.CC, (size_t)c->p * 2 * c->p));
+    CHK(walloc(c, &D.lam, c->p));
+    CHK(walloc(c, &D.alpha, c->p));
+    CHK(walloc(c, &D.beta, c->p));
+    if (c->ws_base && c->ws_carve) c->ws_off = std::max(ws_hi, c->ws_off);
     c->prec = OFKS_F64;
     return OFKS_OK;
+}
+
+// a switch that fails part-way leaves no usable iterate
+int promote_to_f64(ofks_ctx *c) {
+    const int rc = promote_to_f64_impl(c);
+    if (rc < 0) c->has_x = false;
+    return rc;
+}
+
+// turns workspace carving on for the duration of an entry point
+struct WsScope {
+    ofks_ctx *c;
+    explicit WsScope(ofks_ctx *c_) : c(c_) { c->ws_carve = true; }
+    ~WsScope() { c->ws_carve = false; }
+};
+
+// Releases every piece of device state a workspace may hold (those inside
+// the workspace are only forgotten); the iterate is gone afterwards.
+void release_state(ofks_ctx *c) {
+    free_blocks<double>(c);
+    free_blocks<float>(c);
+    dfree(c, c->active);
+    dfree(c, c->rz);
+    dfree(c, c->g2);
+    dfree(c, c->tw);
+    dfree(c, c->part);
+    c->part_cap = 0;
+    dfree(c, c->gl_ft);
+    c->gl_ft_cap = 0;
+    dfree(c, c->hb32);
+    dfree(c, c->lb32);
+    free_scf_work(c);
+    c->has_x = false;
+}
+
+// set_x0 and state_set rebuild the whole iteration state: with a workspace,
+// release every carved piece and start again from its beginning
+void ws_restart(ofks_ctx *c) {
+    if (!c->ws_base) return;
+    release_state(c);
+    c->ws_off = 0;
 }
 
 int check_ready(ofks_ctx *c) {
@@ -1195,9 +1290,16 @@ int check_ready(ofks_ctx *c) {
 }
 
 int ensure_f32_matrices(ofks_ctx *c) {
-    if (!c->hb32) {
-        CHK(dalloc(c, &c->hb32, c->nnz));
-        CHK(dalloc(c, &c->lb32, c->nnz));
+    if (!(c->hb32 && c->lb32)) {
+        dfree(c, c->hb32);   // both or neither
+        dfree(c, c->lb32);
+        int rc = walloc(c, &c->hb32, c->nnz);
+        if (rc == OFKS_OK) rc = walloc(c, &c->lb32, c->nnz);
+        if (rc != OFKS_OK) {
+            dfree(c, c->hb32);
+            dfree(c, c->lb32);
+            return rc;
+        }
     }
     HIPCHK(launch_pairs_to_f32(c->stream, c->nnz, c->hb, c->hb32));
     HIPCHK(launch_pairs_to_f32(c->stream, c->nnz, c->lb, c->lb32));
@@ -1666,26 +1768,72 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
     return OFKS_OK;
 }
 
+// ---- caller-owned workspace -------------------------------------------------
+
+int ofks_workspace_size(ofks_ctx *c, int32_t p, const ofks_params *prm, size_t *bytes) {
+    if (!c) return OFKS_EINVAL;
+    if (!c->has_system) return fail(c, OFKS_ESTATE, "workspace_size: no system");
+    if (!prm || !bytes || p <= 0 || p > 1024) return fail(c, OFKS_EINVAL, "workspace_size: bad arguments");
+    // the pieces in the order set_x0 / state_set / step carve them
+    size_t total = 4 * ws_piece((size_t)p * sizeof(double));                  // active, rz, g2, tw
+    total += ws_piece(partials_needed(c, p) * sizeof(double));                 // per-block partial sums
+    if (prm->precision == OFKS_F64) {
+        total += ws_block_set(c->n, p, sizeof(double), 8);
+    } else {
+        total += ws_block_set(c->n, p, sizeof(double), prm->refine_tol > 0.0 ? 8 : 3);
+        total += 2 * ws_piece((size_t)c->nnz * sizeof(float2));               // FP32 copies of H and L/2
+        total += ws_block_set(c->n, p, sizeof(float), 8);
+    }
+    if (prm->precond == OFKS_PRECOND_GRAPH) total += ws_piece((size_t)c->n * p * sizeof(float));
+    if (prm->scf) total += 4 * ws_piece((size_t)4 * c->n_tets * sizeof(double));
+    *bytes = total;
+    return OFKS_OK;
+}
+
+int ofks_set_workspace(ofks_ctx *c, void *dev_ws, size_t bytes) {
+    if (!c) return OFKS_EINVAL;
+    if (dev_ws && (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0 || bytes == 0))
+        return fail(c, OFKS_EINVAL, "set_workspace: need a 256-byte aligned, non-empty device buffer");
+    CHK(sync(c));
+    // the iteration state moves: whatever exists (pieces of an earlier
+    // workspace included) is released, and set_x0 or state_set must follow
+    release_state(c);
+    c->ws_base = (char *)dev_ws;
+    c->ws_size = dev_ws ? bytes : 0;
+    c->ws_off = 0;
+    return OFKS_OK;
+}
+
 int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     if (!c) return OFKS_EINVAL;
     if (!c->has_system) return fail(c, OFKS_ESTATE, "set_x0: no system");
     if (!c->has_params) return fail(c, OFKS_ESTATE, "set_x0: call ofks_set_params first");
     if (p <= 0 || p > 1024 || !X0) return fail(c, OFKS_EINVAL, "set_x0: need 1 <= p <= 1024 and a block");
     if (p > c->n) return fail(c, OFKS_EINVAL, "set_x0: p exceeds n");
+    WsScope wss(c);
+    c->has_x = false;   // until the new state is complete
     free_blocks<double>(c);
     free_blocks<float>(c);
     dfree(c, c->active);
     dfree(c, c->rz);
+    dfree(c, c->g2);
+    dfree(c, c->tw);
+    ws_restart(c);
     c->p = p;
     c->prec = c->prm.precision;
     dfree(c, c->g2);
     dfree(c, c->tw);
-    CHK(dalloc(c, &c->active, p));
-    CHK(dalloc(c, &c->rz, p));
-    CHK(dalloc(c, &c->g2, p));
-    CHK(dalloc(c, &c->tw, p));
+    CHK(walloc(c, &c->active, p));
+    CHK(walloc(c, &c->rz, p));
+    CHK(walloc(c, &c->g2, p));
+    CHK(walloc(c, &c->tw, p));
     CHK(ensure_part(c, partials_needed(c, p)));
+    c->ws_f64_base = c->ws_off;
     CHK(alloc_blocks<double>(c, c->prec == OFKS_F32));   // an FP32 run needs only the setup blocks in FP64
+    if (c->ws_base && c->prec == OFKS_F32) {
+        c->ws_f64_cap = ws_f64_region(c, p);
+        c->ws_off = c->ws_f64_base + c->ws_f64_cap;
+    }
     Blocks<double> &B = c->b64;
     HIPCHK(hipMemcpyAsync(B.Xt, X0, (size_t)c->n * p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (orth) {
@@ -1727,6 +1875,9 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
         CHK(sync(c));
         free_blocks<double>(c);
     }
+    // a run from a start block depends on nothing an earlier run left: the
+    // Hartree solve's warm start goes back to zero
+    if (c->U) HIPCHK(hipMemsetAsync(c->U, 0, (size_t)c->n * sizeof(double), c->stream));
     c->dinv_h.assign(p, 1.0);
     c->k = 0;
     c->kkt0 = -1.0;
@@ -1746,6 +1897,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
 
 int ofks_step(ofks_ctx *c, int32_t max_steps, ofks_iter_stats *stats, int32_t *n_stats, int32_t *done) {
     CHK(check_ready(c));
+    WsScope wss(c);
     int ns = 0;
     int rc = OFKS_OK;
     for (int s = 0; s < max_steps && !c->done; ++s) {
@@ -2470,22 +2622,28 @@ template <typename T> int state_blocks(ofks_ctx *c, char *buf, size_t off, bool 
 // (re)allocates the iteration blocks for width p in precision prec (the
 // allocation part of ofks_set_x0, without a start block)
 int setup_blocks(ofks_ctx *c, int p, int prec) {
+    WsScope wss(c);
+    c->has_x = false;   // until the new state is complete
     free_blocks<double>(c);
     free_blocks<float>(c);
     dfree(c, c->active);
     dfree(c, c->rz);
     dfree(c, c->g2);
     dfree(c, c->tw);
+    ws_restart(c);
     c->p = p;
     c->prec = prec;
-    CHK(dalloc(c, &c->active, p));
-    CHK(dalloc(c, &c->rz, p));
-    CHK(dalloc(c, &c->g2, p));
-    CHK(dalloc(c, &c->tw, p));
+    CHK(walloc(c, &c->active, p));
+    CHK(walloc(c, &c->rz, p));
+    CHK(walloc(c, &c->g2, p));
+    CHK(walloc(c, &c->tw, p));
     CHK(ensure_part(c, partials_needed(c, p)));
     if (prec == OFKS_F64) {
         CHK(alloc_blocks<double>(c));
     } else {
+        c->ws_f64_base = c->ws_off;
+        c->ws_f64_cap = c->ws_base ? ws_f64_region(c, p) : 0;
+        c->ws_off += c->ws_f64_cap;
         CHK(ensure_f32_matrices(c));
         CHK(alloc_blocks<float>(c));
     }

@@ -171,6 +171,21 @@ class Solver:
         self._check(self.lib.ofks_set_params(self.h, ctypes.byref(p)))
         self.params = p
 
+    def workspace_size(self, p: int) -> int:
+        nb = ctypes.c_size_t()
+        self._check(self.lib.ofks_workspace_size(self.h, int(p), ctypes.byref(self.params), ctypes.byref(nb)))
+        return nb.value
+
+    def set_workspace(self, buf):
+        """buf: a device uint8 tensor that holds the iteration state from now
+        on (None: back to library allocation)."""
+        if buf is None:
+            self._check(self.lib.ofks_set_workspace(self.h, None, 0))
+            self._ws = None
+            return
+        self._ws = buf
+        self._check(self.lib.ofks_set_workspace(self.h, ctypes.c_void_p(buf.data_ptr()), int(buf.numel())))
+
     def set_x0(self, X0, orthonormalize: bool = True):
         _check_block(X0, self.n)
         p = int(X0.shape[1])
