@@ -226,8 +226,9 @@ def test_what_the_network_gains_over_the_method_without_it():
 
     With the fallbacks on (the production setting: the paper preconditioner
     takes over when the energy rises or the residual stalls), the shipped
-    trained network reaches rel 1e-6 within 1500 iterations, where the method
-    without a preconditioner does not.  With the fallbacks off, the learned
+    trained network reaches rel 1e-6 in fewer than half the iterations of
+    the method without a preconditioner (on the device: 409 against 1370).
+    With the fallbacks off, the learned
     form's structure alone (the untrained network, the Jacobi of T) is three
     orders of magnitude ahead of no preconditioner after 300 iterations.
     Wall times beside the paper preconditioner's are printed, not asserted: a
@@ -262,8 +263,8 @@ def test_what_the_network_gains_over_the_method_without_it():
         st, dt = run(pre, wts, 1500, 1e-6)
         out[tag] = (len(st) - 1, st[-1]["rel"], dt, sum(x["fell_back"] for x in st))
     print("[gpu] to rel 1e-6 (iterations, rel, seconds, fallbacks): " + str(out), flush=True)
-    assert out["trained"][1] < 1e-6
-    assert out["none"][1] > 1e-6
+    assert out["trained"][1] < 1e-6 and out["none"][1] < 1e-6
+    assert out["trained"][0] < 0.5 * out["none"][0]
     alone = {}
     for tag, pre, wts in (("none", "none", None), ("untrained", "learned", untrained)):
         st, _ = run(pre, wts, 300, 1e-30, fallbacks=False)
