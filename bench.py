@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "u2", "u3"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--pcg-iters", type=int, default=10)
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-residual runs")
@@ -353,7 +353,7 @@ def main():
     from paper_2007_14228_amd import Solver
 
     t = time.perf_counter()
-    w = wl.make_workload(a.workload, seed=a.seed)
+    w = wl.make_workload(a.workload, seed=a.seed, **({"progress": log} if a.workload.startswith("u") else {}))
     n = w.mesh.n_dofs
     p = w.p
     log(f"workload {a.workload}: n={n} p={p} tets={w.mesh.n_tets} ({time.perf_counter() - t:.1f}s)")

@@ -13,6 +13,10 @@ gamma2), applied per axis with r_j the distance along that axis, which is a
 lower bound on the 3-D distance and therefore refines at least as much as the
 law asks.  Nodes on the boundary of the box carry the homogeneous Dirichlet
 condition of the H^1_0 space (Section 2.2).
+
+Unstructured graded meshes (the kind the paper builds with a mesh generator
+from the same law) apply the law in 3-D distance to an octree, jitter its
+vertices and join them by a Delaunay tetrahedralization.
 """
 from __future__ import annotations
 
@@ -28,6 +32,9 @@ __all__ = [
     "uniform_axis",
     "graded_axis",
     "kuhn_mesh",
+    "unstructured_mesh",
+    "unstructured_mesh_for_dofs",
+    "tet_quality",
     "sample_cluster",
     "random_block",
     "random_block_chunks",
@@ -149,13 +156,18 @@ for _perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
     _KUHN_PATHS.append(_path)
 
 
-def _morton_rank(I: np.ndarray, J: np.ndarray, K: np.ndarray) -> np.ndarray:
-    """Rank of each (i, j, k) along the Z-order (bit-interleaved) curve."""
+def _morton_code(I: np.ndarray, J: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Z-order (bit-interleaved) code of each (i, j, k), 21 bits per axis."""
     code = np.zeros(I.shape, dtype=np.uint64)
     for b in range(21):
         for d, A in enumerate((I, J, K)):
             code |= ((A.astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + d)
-    order = np.argsort(code, kind="stable")
+    return code
+
+
+def _morton_rank(I: np.ndarray, J: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Rank of each (i, j, k) along the Z-order (bit-interleaved) curve."""
+    order = np.argsort(_morton_code(I, J, K), kind="stable")
     rank = np.empty_like(order)
     rank[order] = np.arange(order.size)
     return rank
@@ -234,6 +246,149 @@ def graded_mesh_for_dofs(half: float, Z: np.ndarray, R: np.ndarray, target_dofs:
             hi = mid
     g1 = lo if abs(dofs(lo) - target_dofs) <= abs(dofs(hi) - target_dofs) else hi
     return graded_mesh(half, Z, R, g1, gamma2, hmin), g1
+
+
+# ----------------------------------------------------------------------------
+# Unstructured graded meshes
+# ----------------------------------------------------------------------------
+
+def _mesh_size(C: np.ndarray, half_edge: float, Z, R, gamma1: float, gamma2: float,
+               hmin: float) -> np.ndarray:
+    """The mesh-size law h = min_j(gamma1 Z_j^{-2/5} r_j^{6/5}, gamma2), clipped
+    below at hmin, at its smallest over each axis-aligned cube (centre C, half
+    edge half_edge): r_j is the distance from nucleus j to the cube."""
+    h = np.full(len(C), float(gamma2))
+    for Rj, Zj in zip(R, Z):
+        d = np.maximum(np.abs(C - Rj) - half_edge, 0.0)
+        h = np.minimum(h, gamma1 * float(Zj) ** (-0.4) * np.linalg.norm(d, axis=1) ** 1.2)
+    return np.clip(h, hmin, gamma2)
+
+
+def octree_lattice(half: float, Z, R, gamma1: float, gamma2: float, hmin: float):
+    """Vertices of an octree over [-half, half]^3 whose cubes are refined until
+    their edge is at most the mesh-size law's h over the cube (or halving would
+    go below hmin).  Returns (P, smin, unit, nmax): integer lattice
+    coordinates [N, 3] of the distinct cube corners, the edge (in lattice units)
+    of the smallest cube at each corner, the lattice step, and the lattice
+    size per axis."""
+    n0 = max(1, int(math.ceil(2.0 * half / gamma2)))
+    s = 2.0 * half / n0
+    g = (np.arange(n0) + 0.5) * s - half
+    C = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    octants = np.array([[dx, dy, dz] for dx in (-1, 1) for dy in (-1, 1) for dz in (-1, 1)], dtype=np.float64)
+    leaves = []
+    level = 0
+    while len(C):
+        split = (s > _mesh_size(C, 0.5 * s, Z, R, gamma1, gamma2, hmin)) & (0.5 * s >= hmin)
+        leaves.append((C[~split], level))
+        C = (C[split][:, None, :] + 0.25 * s * octants[None]).reshape(-1, 3)
+        s *= 0.5
+        level += 1
+    finest = level - 1
+    unit = 2.0 * half / (n0 * 2 ** finest)
+    nmax = n0 * 2 ** finest
+    corners = np.array([[dx, dy, dz] for dx in (0, 1) for dy in (0, 1) for dz in (0, 1)], dtype=np.int64)
+    pts, sizes = [], []
+    for Cl, lv in leaves:
+        if len(Cl):
+            m = 2 ** (finest - lv)
+            lo = np.rint((Cl + half) / unit - 0.5 * m).astype(np.int64)
+            pts.append((lo[:, None, :] + corners[None] * m).reshape(-1, 3))
+            sizes.append(np.full(8 * len(Cl), m, dtype=np.int64))
+    P = np.concatenate(pts)
+    S = np.concatenate(sizes)
+    key = (P[:, 0] * (nmax + 1) + P[:, 1]) * (nmax + 1) + P[:, 2]
+    uk, inv = np.unique(key, return_inverse=True)
+    smin = np.full(len(uk), np.iinfo(np.int64).max, dtype=np.int64)
+    np.minimum.at(smin, inv, S)
+    Pu = np.empty((len(uk), 3), dtype=np.int64)
+    Pu[inv] = P
+    return Pu, smin, unit, nmax
+
+
+def tet_quality(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
+    """6 sqrt(2) |K| / (longest edge)^3: 1 for the regular tetrahedron, -> 0
+    for a flat one."""
+    v = xyz[tets]
+    vol = np.abs(np.einsum("ij,ij->i", v[:, 1] - v[:, 0], np.cross(v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]))) / 6.0
+    e = np.stack([np.linalg.norm(v[:, a] - v[:, b], axis=1)
+                  for a, b in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))], axis=1)
+    return 6.0 * math.sqrt(2.0) * vol / e.max(axis=1) ** 3
+
+
+def unstructured_mesh(half: float, Z, R, gamma1: float, gamma2: float, hmin: float, seed: int = 0,
+                      jitter: float = 0.3, qmin: float = 0.02, rounds: int = 12, progress=None) -> Mesh:
+    """Unstructured graded tetrahedral mesh of [-half, half]^3 following the
+    mesh-size law in 3-D distance.
+
+    The octree's cube corners (octree_lattice) are moved by a seeded uniform
+    offset of up to jitter x the smallest adjacent cube edge per coordinate
+    (points on the box faces move only within their face), then joined by
+    the Delaunay tetrahedralization (scipy.spatial.Delaunay, Qhull).  Slivers
+    (quality below qmin) are removed by drawing new offsets for their
+    interior vertices and triangulating again, for at most `rounds` rounds.
+    Nodes are numbered along the Z-order curve of their lattice coordinates
+    (neighbours get nearby numbers), tetrahedra are positively oriented and
+    ordered by their lowest node.  Nodes on the box faces carry the
+    homogeneous Dirichlet condition.  progress(str), if given, is called
+    after each triangulation."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    P, smin, unit, nmax = octree_lattice(half, Z, R, gamma1, gamma2, hmin)
+    order = np.argsort(_morton_code(P[:, 0], P[:, 1], P[:, 2]), kind="stable")
+    P, smin = P[order], smin[order]
+    fixed = (P == 0) | (P == nmax)
+    onb = fixed.any(axis=1)
+    amp = jitter * smin * unit
+
+    def draw(idx):
+        J = rng.uniform(-1.0, 1.0, (len(idx), 3)) * amp[idx, None]
+        J[fixed[idx]] = 0.0
+        return J
+
+    off = draw(np.arange(len(P)))
+    for _ in range(rounds + 1):
+        xyz = P * unit - half + off
+        T = Delaunay(xyz).simplices.astype(np.int64)
+        q = tet_quality(xyz, T)
+        bad = np.unique(T[q < qmin].ravel())
+        bad = bad[~onb[bad]]
+        if progress:
+            progress(f"Delaunay: {len(P)} points, {len(T)} tetrahedra, quality min {q.min():.3g}, "
+                     f"{len(bad)} vertices of slivers")
+        if not len(bad):
+            break
+        off[bad] = draw(bad)
+    if q.min() <= 0.0:
+        raise RuntimeError("degenerate tetrahedron in the Delaunay mesh")
+    v = xyz[T]
+    det = np.einsum("ij,ij->i", v[:, 1] - v[:, 0], np.cross(v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]))
+    neg = det < 0
+    T[neg] = T[neg][:, [0, 2, 1, 3]]
+    T = T[np.argsort(T.min(axis=1), kind="stable")]
+    return Mesh(xyz=xyz, tets=T.astype(np.int32), dirichlet=onb.astype(np.uint8), cells=())
+
+
+def unstructured_mesh_for_dofs(half: float, Z, R, target_dofs: int, gamma2: float, hmin: float,
+                               seed: int = 0, iters: int = 30, progress=None) -> tuple:
+    """Bisection on gamma1 so that the interior node count of the octree
+    lattice is close to target_dofs, then unstructured_mesh."""
+
+    def dofs(g1):
+        P, _, _, nmax = octree_lattice(half, Z, R, g1, gamma2, hmin)
+        return int(np.sum(~((P == 0) | (P == nmax)).any(axis=1)))
+
+    lo, hi = 1e-3, 50.0
+    for _ in range(iters):
+        mid = math.sqrt(lo * hi)
+        if dofs(mid) > target_dofs:
+            lo = mid
+        else:
+            hi = mid
+    g1 = lo if abs(dofs(lo) - target_dofs) <= abs(dofs(hi) - target_dofs) else hi
+    if progress:
+        progress(f"mesh-size law: gamma1 = {g1:.4g}")
+    return unstructured_mesh(half, Z, R, g1, gamma2, hmin, seed=seed, progress=progress), g1
 
 
 # ----------------------------------------------------------------------------
@@ -326,8 +481,30 @@ def _c4(seed: int = 0, target_dofs: int = 8_000_000, p: int = 512) -> Workload:
     return w
 
 
+def _u2(seed: int = 0, target_dofs: int = 200_000, progress=None) -> Workload:
+    Z, R = sample_cluster(seed, 4, (1, 6, 8), 3.0, 2.0)
+    mesh, g1 = unstructured_mesh_for_dofs(10.0, Z, R, target_dofs, gamma2=1.5, hmin=0.05, seed=seed,
+                                          progress=progress)
+    p = int(math.ceil(Z.sum() / 2.0))
+    return Workload("u2", mesh, Z, R, p=p, beta=1.0, scf=True, seed=seed,
+                    notes=f"4 nuclei, unstructured graded (Delaunay), gamma1={g1:.4g}")
+
+
+def _u3(seed: int = 0, target_dofs: int = 500_000, p: int = 128, M: int = 24, progress=None) -> Workload:
+    a = _cluster_box(M)
+    Z, R = sample_cluster(seed, M, (1, 6, 7, 8), a, 2.0)
+    mesh, g1 = unstructured_mesh_for_dofs(a + 7.0, Z, R, target_dofs, gamma2=1.5, hmin=0.05, seed=seed,
+                                          progress=progress)
+    return Workload("u3", mesh, Z, R, p=p, beta=1.0, scf=False, seed=seed,
+                    notes=f"{M} nuclei in [-{a:.3g},{a:.3g}]^3, unstructured graded (Delaunay), gamma1={g1:.4g}")
+
+
 def make_workload(name: str, seed: int = 0, **kw) -> Workload:
     name = name.lower()
+    if name == "u2":
+        return _u2(seed, **kw)
+    if name == "u3":
+        return _u3(seed, **kw)
     if name == "c1":
         return _c1(seed, **kw)
     if name == "c2":
@@ -347,4 +524,6 @@ CONFIGS = {
     "c3": "24 nuclei Z in {1,6,7,8}, graded grid n~2e6, p=128, fixed H (precision form)",
     "c4": "96 nuclei, graded grid n~8e6, p=512, fixed H (precision form at scale)",
     "c5": "c3-type held-out clusters (seeds 2000..2019), learned-preconditioner evaluation",
+    "u2": "c2's 4-nucleus clusters on an unstructured graded Delaunay mesh, n~2e5, full SCF LDA",
+    "u3": "c3's 24-nucleus clusters on an unstructured graded Delaunay mesh, n~5e5, p=128, fixed H",
 }
