@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-baseline", default="auto", choices=["auto", "skip"])
     ap.add_argument("--max-iter", type=int, default=1500)
+    ap.add_argument("--energy-legs", default="both", choices=["both", "fp64", "mixed"],
+                    help="which runs --energy-check makes (one per process for the largest workloads)")
     ap.add_argument("--energy-check", type=float, default=0.0,
                     help="also run FP64 and mixed precision to this residual and report the energy difference")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -268,16 +270,40 @@ def traffic_from_profiles(kernel, workload):
                 fetch_scale=rec.get("fetch_scale"), write_scale=rec.get("write_scale"))
 
 
-def run_to_tol(torch, s, X0, tol, params, weights=None):
+def set_start(torch, s, X0):
+    """set_x0 from a device block, or from a callable that makes one; a block
+    made here is released before the first step (the library allocates the
+    rest of its FP64 blocks then), which the largest workloads need."""
+    if callable(X0):
+        X = X0()
+        s.set_x0(X, orthonormalize=True)
+        del X
+        torch.cuda.empty_cache()
+    else:
+        s.set_x0(X0, orthonormalize=True)
+    torch.cuda.synchronize()
+
+
+def run_to_tol(torch, s, X0, tol, params, weights=None, chunk=100):
     """Seconds from the first step to the first iterate with residual < tol
-    (setup excluded; X0 B-orthonormalized before the clock starts)."""
+    (setup excluded; X0 B-orthonormalized before the clock starts).  The
+    steps are taken `chunk` at a time (the iteration state carries over), with
+    a progress line after each chunk once a run has taken 20 s."""
     s.set_params(tol=tol, **params)
     if weights is not None:
         s.lp_set_weights(*weights)
-    s.set_x0(X0, orthonormalize=True)
-    torch.cuda.synchronize()
+    set_start(torch, s, X0)
     t0 = time.perf_counter()
-    stats, done, rc = s.step(params.get("max_iter", 1000) + 1)
+    stats = []
+    left = params.get("max_iter", 1000) + 1
+    while left > 0:
+        st, done, rc = s.step(min(chunk, left))
+        stats += st
+        left -= len(st)
+        if done or not st:
+            break
+        if time.perf_counter() - t0 > 20.0:
+            log(f"    {len(stats)} iterations, rel {st[-1]['rel']:.3e} ({time.perf_counter() - t0:.0f} s)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     last = stats[-1]
@@ -358,7 +384,9 @@ def main():
     p = w.p
     log(f"workload {a.workload}: n={n} p={p} tets={w.mesh.n_tets} ({time.perf_counter() - t:.1f}s)")
     X0_host = wl.random_block(1000 + a.seed, n, p)
-    X0 = torch.from_numpy(X0_host).to("cuda")
+
+    def X0():
+        return torch.from_numpy(X0_host).to("cuda")
 
     s = Solver()
     t = time.perf_counter()
@@ -368,7 +396,7 @@ def main():
     params = dict(beta=w.beta, precond="paper", pcg_iters=a.pcg_iters, max_iter=a.max_iter,
                   scf=1 if w.scf else 0, energy_every=10 if p > 64 else 1)
     s.set_params(tol=1e-30, **params)
-    s.set_x0(X0, orthonormalize=True)
+    set_start(torch, s, X0)
     s.step(a.warmup)
     s.timing(True)
     torch.cuda.synchronize()
@@ -462,7 +490,7 @@ def main():
     if a.jsonl:
         log(f"per-iteration log: {a.jsonl}")
         s.set_params(tol=1e-30, **params)
-        s.set_x0(X0, orthonormalize=True)
+        set_start(torch, s, X0)
         jsonl_log(torch, s, a.steps, a.jsonl)
     if a.study_m:
         log(f"inner-solve length study, {a.workload}: m = {a.study_m}")
@@ -480,15 +508,18 @@ def main():
         # the precision form's energy error, both runs converged well past 1e-6
         tol = a.energy_check
         ep = dict(params, max_iter=max(a.max_iter, 4000))
-        log(f"energy check at residual {tol:g}: FP64")
-        e64 = run_to_tol(torch, s, X0, tol, ep)
-        log(f"  {e64}")
-        log(f"energy check at residual {tol:g}: mixed precision")
-        e32 = run_to_tol(torch, s, X0, tol, dict(ep, precision="f32", refine_tol=1e-5))
-        log(f"  {e32}")
+        e64 = e32 = None
+        if a.energy_legs in ("both", "fp64"):
+            log(f"energy check at residual {tol:g}: FP64")
+            e64 = run_to_tol(torch, s, X0, tol, ep)
+            log(f"  {e64}")
+        if a.energy_legs in ("both", "mixed"):
+            log(f"energy check at residual {tol:g}: mixed precision")
+            e32 = run_to_tol(torch, s, X0, tol, dict(ep, precision="f32", refine_tol=1e-5))
+            log(f"  {e32}")
         out["energy_check"] = {"tol": tol, "fp64": e64, "mixed": e32,
-                               "dE_Ha": abs(e32["energy"] - e64["energy"]) if e64["converged"] and e32["converged"]
-                               else None}
+                               "dE_Ha": abs(e32["energy"] - e64["energy"])
+                               if e64 and e32 and e64["converged"] and e32["converged"] else None}
     s.close()
 
     if a.cpu_baseline == "auto":

@@ -168,7 +168,11 @@ int ofks_set_workspace(ofks_ctx *ctx, void *dev_ws, size_t bytes);
 
 /* Starting block X0 (device f64[n*p]).  b_orthonormalize = 1 applies the
  * Cholesky-based Gram-Schmidt of Section 4.2 (X0 = V R^{-1}, R^T R = V^T B V);
- * 0 takes X0 as given.  Allocates the iteration blocks for this p.  Resets
+ * 0 takes X0 as given.  Allocates the iteration blocks for this p (for an
+ * FP64 run the three the orthonormalization uses; the other five come with
+ * the first ofks_step, ofks_state_get or ofks_postprocess, so the caller may
+ * free X0 in between: the eight FP64 blocks of n = 8e6, p = 512 take 262 GB
+ * of the 288, X0 another 33).  Resets
  * the iteration counter, the fallback history and the Hartree solve's warm
  * start, so the run depends only on X0 and the parameters.  ENOTSPD if V^T B V is not positive definite;
  * EZERONORM if a column taken as given has zero B-norm. */

@@ -1250,9 +1250,34 @@ int promote_to_f64(ofks_ctx *c) {
 // turns workspace carving on for the duration of an entry point
 struct WsScope {
     ofks_ctx *c;
-    explicit WsScope(ofks_ctx *c_) : c(c_) { c->ws_carve = true; }
-    ~WsScope() { c->ws_carve = false; }
+    bool prev;
+    explicit WsScope(ofks_ctx *c_) : c(c_), prev(c_->ws_carve) { c->ws_carve = true; }
+    ~WsScope() { c->ws_carve = prev; }
 };
+
+// An FP64 run's set_x0 allocates only the three blocks the start block's
+// orthonormalization uses; the other five come with the first call that
+// needs them, so a caller can release its start block in between (at
+// n = 8e6, p = 512 the eight FP64 blocks take 262 GB of the 288).
+int complete_blocks(ofks_ctx *c) {
+    if (c->prec != OFKS_F64 || c->b64.Xp) return OFKS_OK;
+    WsScope wss(c);
+    Blocks<double> &B = c->b64;
+    const size_t np = (size_t)c->n * c->p;
+    int rc = walloc(c, &B.Xp, np);
+    if (rc == OFKS_OK) rc = walloc(c, &B.P, np);
+    if (rc == OFKS_OK) rc = walloc(c, &B.Pp, np);
+    if (rc == OFKS_OK) rc = walloc(c, &B.R, np);
+    if (rc == OFKS_OK) rc = walloc(c, &B.D, np);
+    if (rc != OFKS_OK) {
+        dfree(c, B.Xp);
+        dfree(c, B.P);
+        dfree(c, B.Pp);
+        dfree(c, B.R);
+        dfree(c, B.D);
+    }
+    return rc;
+}
 
 // Releases every piece of device state a workspace may hold (those inside
 // the workspace are only forgotten); the iterate is gone afterwards.
@@ -1829,7 +1854,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
     CHK(walloc(c, &c->tw, p));
     CHK(ensure_part(c, partials_needed(c, p)));
     c->ws_f64_base = c->ws_off;
-    CHK(alloc_blocks<double>(c, c->prec == OFKS_F32));   // an FP32 run needs only the setup blocks in FP64
+    CHK(alloc_blocks<double>(c, true));   // the start block's setup; complete_blocks adds the rest
     if (c->ws_base && c->prec == OFKS_F32) {
         c->ws_f64_cap = ws_f64_region(c, p);
         c->ws_off = c->ws_f64_base + c->ws_f64_cap;
@@ -1898,6 +1923,7 @@ int ofks_set_x0(ofks_ctx *c, int32_t p, const double *X0, int32_t orth) {
 int ofks_step(ofks_ctx *c, int32_t max_steps, ofks_iter_stats *stats, int32_t *n_stats, int32_t *done) {
     CHK(check_ready(c));
     WsScope wss(c);
+    CHK(complete_blocks(c));
     int ns = 0;
     int rc = OFKS_OK;
     for (int s = 0; s < max_steps && !c->done; ++s) {
@@ -1991,7 +2017,11 @@ int ofks_get_x(ofks_ctx *c, double *dev_X) {
 
 int ofks_postprocess(ofks_ctx *c, double *eigs) {
     CHK(check_ready(c));
-    if (c->prec != OFKS_F64) CHK(promote_to_f64(c));
+    if (c->prec != OFKS_F64) {
+        WsScope wss(c);
+        CHK(promote_to_f64(c));
+    }
+    CHK(complete_blocks(c));
     Blocks<double> &B = c->b64;
     const int p = c->p;
     // normalized current iterate into Xt
@@ -2680,6 +2710,7 @@ int ofks_state_size(ofks_ctx *c, size_t *bytes) {
 
 int ofks_state_get(ofks_ctx *c, void *dev_buf, size_t bytes) {
     CHK(check_ready(c));
+    CHK(complete_blocks(c));
     size_t need = 0;
     CHK(ofks_state_size(c, &need));
     if (!dev_buf || bytes < need) return fail(c, OFKS_EINVAL, "state_get: need a device buffer of %zu bytes", need);
