@@ -271,10 +271,13 @@ def traffic_from_profiles(kernel, workload):
 
 
 def set_start(torch, s, X0):
-    """set_x0 from a device block, or from a callable that makes one; a block
-    made here is released before the first step (the library allocates the
-    rest of its FP64 blocks then), which the largest workloads need."""
+    """set_x0 from a device block, or from a callable that makes one; then
+    the previous run's blocks are released before the block is made, and the
+    block is released before the first step (the library allocates the rest
+    of its FP64 blocks then), which the largest workloads need."""
     if callable(X0):
+        s.set_workspace(None)   # releases the previous run's blocks first
+        torch.cuda.synchronize()
         X = X0()
         s.set_x0(X, orthonormalize=True)
         del X
