@@ -380,28 +380,36 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int p, int64_t row
 #ifndef OFKS_RG_WPE
 #define OFKS_RG_WPE 2
 #endif
-template <typename T, int NTW, int EPI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OFKS_RG_WPE)))
+// CT column tiles per block: with CT = 2 a 512-thread block computes both
+// 16 NTW-column tiles of its row tile (waves 0-3 the first, 4-7 the second),
+// so A (and the epilogue's HX) is read once for 2 TC output columns instead
+// of once per column tile.
+// (FP32 blocks: four waves per SIMD, which the two-tile block needs asked for
+// explicitly; the one-tile block reaches it within the two-wave budget.)
+template <typename T, int NTW, int EPI, int CT>
+__global__ __launch_bounds__(256 * CT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && CT == 2 ? 4 : OFKS_RG_WPE)))
 void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *__restrict__ sa,
                     const T *__restrict__ M, T *__restrict__ Y, GradArgs ga) {
-    constexpr int TR = 64, TC = 16 * NTW, KC = OFKS_RG_KC;
+    constexpr int TR = 64, TC = 16 * NTW, KC = OFKS_RG_KC, TCB = TC * CT, NTH = 256 * CT;
     using acc_t = typename mfma4<T>::type;
     __shared__ T As[TR][KC + 1];
-    __shared__ T Ms[KC][TC];
-    __shared__ double red[256];
-    // per-column epilogue constants of this block's column tile, fixed for the
+    __shared__ T Ms[KC][TCB];
+    __shared__ double red[NTH];
+    // per-column epilogue constants of this block's columns, fixed for the
     // launch (in LDS rather than registers: it keeps more waves resident)
-    __shared__ T scl_s[TC], lmc_s[TC];
-    __shared__ uint8_t act_s[TC];
+    __shared__ T scl_s[TCB], lmc_s[TCB];
+    __shared__ uint8_t act_s[TCB];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = w & 3, ct = w >> 2;   // row group and column tile of this wave
     const int li = lane & 15, lk = lane >> 4;
-    const int c0 = blockIdx.y * TC;
+    const int c0 = blockIdx.y * TCB;
+    const int cw = ct * TC;              // this wave's first column within the block
     const int64_t ntiles = (n + TR - 1) / TR;
     double r2 = 0.0;
     double rz[NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) rz[t] = 0.0;
-    for (int cl = threadIdx.x; cl < TC; cl += 256) {
+    for (int cl = threadIdx.x; cl < TCB; cl += NTH) {
         const int c = c0 + cl;
         const int cc = c < p ? c : c - p;
         scl_s[cl] = (EPI != EPI_PLAIN && c < N) ? sa[cc] : T(0);
@@ -416,31 +424,37 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
 
     // K-chunk staging, software-pipelined: the values of the next chunk (of
     // this tile, or the next tile's first) are loaded into registers before
-    // the current chunk's MFMAs and stored to LDS after them
-    // Thread t moves AR consecutive k of one A row and MR consecutive columns
-    // of one M row per chunk (16-byte loads when the chunk is whole and the
-    // rows are 16-byte aligned; element loads with bounds otherwise).
+    // the current chunk's MFMAs and stored to LDS after them.
+    // Threads 0-255 move AR consecutive k of one A row; every thread moves MR
+    // consecutive columns of one M row (of column tile tid / 256) per chunk
+    // (16-byte loads when the chunk is whole and the rows are 16-byte
+    // aligned; element loads with bounds otherwise).
     constexpr int AR = TR * KC / 256, MR = KC * TC / 256;
     static_assert(AR * 256 == TR * KC && MR * 256 == KC * TC && KC % AR == 0 && TC % MR == 0, "chunk split");
     constexpr int VWT = 16 / sizeof(T);
     static_assert(AR % VWT == 0 && MR % VWT == 0, "16-byte pieces");
-    const int a_rr = threadIdx.x * AR / KC, a_kk = threadIdx.x * AR % KC;
-    const int m_kk = threadIdx.x * MR / TC, m_cc = threadIdx.x * MR % TC;
+    const int tm = threadIdx.x & 255;
+    const bool a_mover = threadIdx.x < 256;
+    const int a_rr = tm * AR / KC, a_kk = tm * AR % KC;
+    const int m_kk = tm * MR / TC, m_cc = tm * MR % TC + (threadIdx.x >> 8) * TC;
     const bool avec = p % VWT == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
-    const bool mvec = N % VWT == 0 && reinterpret_cast<uintptr_t>(M) % 16 == 0 && c0 + TC <= N;
+    const bool mvec = N % VWT == 0 && reinterpret_cast<uintptr_t>(M) % 16 == 0 && c0 + TCB <= N;
     T ar[AR], mr[MR];
     auto load_chunk = [&](int64_t tile, int k0) {
-        const int64_t r = tile * TR + a_rr;
         const bool kin = k0 + KC <= p;
-        if (avec && kin && r < n) {
+        if (a_mover) {
+            const int64_t r = tile * TR + a_rr;
+            if (avec && kin && r < n) {
 #pragma unroll
-            for (int q = 0; q < AR; q += VWT) load_vec<T, VWT>(A + r * p + k0 + a_kk + q, *reinterpret_cast<T(*)[VWT]>(&ar[q]));
-        } else {
+                for (int q = 0; q < AR; q += VWT)
+                    load_vec<T, VWT>(A + r * p + k0 + a_kk + q, *reinterpret_cast<T(*)[VWT]>(&ar[q]));
+            } else {
 #pragma unroll
-            for (int j = 0; j < AR; ++j) ar[j] = (r < n && k0 + a_kk + j < p) ? A[r * p + k0 + a_kk + j] : T(0);
+                for (int j = 0; j < AR; ++j) ar[j] = (r < n && k0 + a_kk + j < p) ? A[r * p + k0 + a_kk + j] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < AR; ++j) ar[j] = k0 + a_kk + j < p ? ar[j] * sa[k0 + a_kk + j] : T(0);
         }
-#pragma unroll
-        for (int j = 0; j < AR; ++j) ar[j] = k0 + a_kk + j < p ? ar[j] * sa[k0 + a_kk + j] : T(0);
         const int k = k0 + m_kk;
         if (mvec && kin) {
 #pragma unroll
@@ -452,8 +466,10 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
         }
     };
     auto store_chunk = [&]() {
+        if (a_mover) {
 #pragma unroll
-        for (int j = 0; j < AR; ++j) As[a_rr][a_kk + j] = ar[j];
+            for (int j = 0; j < AR; ++j) As[a_rr][a_kk + j] = ar[j];
+        }
 #pragma unroll
         for (int j = 0; j < MR; ++j) Ms[m_kk][m_cc + j] = mr[j];
     };
@@ -472,16 +488,16 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
             if (nt < ntiles) load_chunk(nt, last ? 0 : k0 + KC);
 #pragma unroll
             for (int s4 = 0; s4 < KC / 4; ++s4) {
-                const T a = As[16 * w + li][4 * s4 + lk];
+                const T a = As[16 * wr + li][4 * s4 + lk];
 #pragma unroll
-                for (int t = 0; t < NTW; ++t) acc[t] = mfma16x16x4(a, Ms[4 * s4 + lk][16 * t + li], acc[t]);
+                for (int t = 0; t < NTW; ++t) acc[t] = mfma16x16x4(a, Ms[4 * s4 + lk][cw + 16 * t + li], acc[t]);
             }
             __syncthreads();
         }
-        // epilogue: lane holds rows r0 + 16w + mfma_row(lk, i) of column c0 + 16 t + li
+        // epilogue: lane holds rows r0 + 16 wr + mfma_row(lk, i) of column c0 + cw + 16 t + li
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int64_t r = r0 + 16 * w + mfma_row<T>(lk, i);
+            const int64_t r = r0 + 16 * wr + mfma_row<T>(lk, i);
             if (r >= n) continue;
             T ld = T(0), bdv = T(0);
             if (EPI == EPI_GRAD_PCG) {
@@ -492,20 +508,21 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
             if (EPI != EPI_PLAIN) {
 #pragma unroll
                 for (int t = 0; t < NTW; ++t) {
-                    const int c = c0 + 16 * t + li;
+                    const int c = c0 + cw + 16 * t + li;
                     hx[t] = c < N ? HX[r * p + (c < p ? c : c - p)] : T(0);
                 }
             }
 #pragma unroll
             for (int t = 0; t < NTW; ++t) {
-                const int c = c0 + 16 * t + li;
+                const int cl = cw + 16 * t + li;
+                const int c = c0 + cl;
                 if (c >= N) continue;
                 const T val = acc[t][i];
                 if (EPI == EPI_PLAIN) {
                     Y[r * N + c] = val;
                     continue;
                 }
-                const T v = fma(hx[t], scl_s[16 * t + li], val);
+                const T v = fma(hx[t], scl_s[cl], val);
                 if (c >= p) {
                     r2 += (double)v * (double)v;
                 } else if (EPI == EPI_GRAD) {
@@ -514,8 +531,8 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
                     Pout[r * p + c] = v;
                     rz[t] += (double)v * (double)v;
                 } else {  // EPI_GRAD_PCG
-                    if (act_s[16 * t + li]) {
-                        const T z = v * (T(1) / (ld - lmc_s[16 * t + li] * bdv));
+                    if (act_s[cl]) {
+                        const T z = v * (T(1) / (ld - lmc_s[cl] * bdv));
                         Rout[r * p + c] = v;
                         Dout[r * p + c] = z;
                         rz[t] += (double)v * (double)z;
@@ -530,23 +547,24 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
     double *part = ga.part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (1 + p);
     red[threadIdx.x] = r2;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = NTH / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[0] = red[0];
     __syncthreads();
     if (EPI == EPI_GRAD_PCG || EPI == EPI_GRAD_NORM) {
-        for (int c = threadIdx.x; c < p; c += 256)
-            if (c < c0 || c >= c0 + TC) part[1 + c] = 0.0;
+        for (int c = threadIdx.x; c < p; c += NTH)
+            if (c < c0 || c >= c0 + TCB) part[1 + c] = 0.0;
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
-            red[threadIdx.x] = rz[t];   // [w][lk][li]
+            red[threadIdx.x] = rz[t];   // [ct][wr][lk][li]
             __syncthreads();
-            if (threadIdx.x < 16) {
+            if (threadIdx.x < 16 * CT) {
+                const int tc = threadIdx.x >> 4, l = threadIdx.x & 15;
                 double sum = 0.0;
-                for (int k = 0; k < 16; ++k) sum += red[k * 16 + threadIdx.x];
-                const int c = c0 + 16 * t + threadIdx.x;
+                for (int k = 0; k < 16; ++k) sum += red[tc * 256 + k * 16 + l];
+                const int c = c0 + tc * TC + 16 * t + l;
                 if (c < p) part[1 + c] = sum;
             }
             __syncthreads();
@@ -937,6 +955,21 @@ int rowgemm_tile_cols(int N) {
     return tc < OFKS_RG_TC_MAX ? tc : OFKS_RG_TC_MAX;
 }
 
+// Column tiles per block of the MFMA row GEMM: two 128-column tiles in one
+// 512-thread block from N = 256 on (A and HX then read once per 256 output
+// columns), one otherwise.
+#ifndef OFKS_RG_CT
+#define OFKS_RG_CT 2
+#endif
+int rowgemm_col_tiles(int N) { return (OFKS_RG_CT == 2 && rowgemm_tile_cols(N) == 128 && N >= 256) ? 2 : 1; }
+
+// blocks along the output columns of launch_rowgemm (its partial sums are
+// gemm_rows x this many blocks)
+int rowgemm_grid_y(int N) {
+    const int w = rowgemm_tile_cols(N) * rowgemm_col_tiles(N);
+    return (N + w - 1) / w;
+}
+
 // number of blocks along rows for k_rowgemm epilogues (fixed => deterministic)
 template <typename T>
 hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int grid_rows, const T *A,
@@ -949,7 +982,8 @@ hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int g
     int gx = grid_rows;
     if (gx > ntiles) gx = (int)ntiles;
     if (gx < 1) gx = 1;
-    const int gy = (N + tc - 1) / tc;
+    const int ct = rowgemm_col_tiles(N);
+    const int gy = (N + tc * ct - 1) / (tc * ct);
     if (gx_out) *gx_out = gx;
     dim3 grid(gx, gy);
 #define OFKS_RG(MT_, NT_)                                                                     \
@@ -963,17 +997,17 @@ hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int g
     OFKS_RG(4, 1)
     OFKS_RG(4, 2)
 #undef OFKS_RG
-#define OFKS_RGM(NTW_)                                                                        \
-    if (nt == NTW_) {                                                                         \
-        if (epi == EPI_PLAIN) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_PLAIN>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
-        else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
-        else if (epi == EPI_GRAD_NORM) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD_NORM>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
-        else hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD_PCG>), grid, dim3(256), 0, s, n, p, N, A, sa, M, Y, ga); \
+#define OFKS_RGM(NTW_, CT_)                                                                   \
+    if (nt == NTW_ && ct == CT_) {                                                            \
+        if (epi == EPI_PLAIN) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_PLAIN, CT_>), grid, dim3(256 * CT_), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD, CT_>), grid, dim3(256 * CT_), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else if (epi == EPI_GRAD_NORM) hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD_NORM, CT_>), grid, dim3(256 * CT_), 0, s, n, p, N, A, sa, M, Y, ga); \
+        else hipLaunchKernelGGL((k_rowgemm_mfma<T, NTW_, EPI_GRAD_PCG, CT_>), grid, dim3(256 * CT_), 0, s, n, p, N, A, sa, M, Y, ga); \
         return hipGetLastError();                                                             \
     }
-    OFKS_RGM(4)
-    OFKS_RGM(8)
-    OFKS_RGM(16)
+    OFKS_RGM(4, 1)
+    OFKS_RGM(8, 1)
+    OFKS_RGM(8, 2)
 #undef OFKS_RGM
     return hipErrorInvalidValue;
 }

@@ -101,6 +101,7 @@ template <typename T>
 hipError_t launch_rowgemm(hipStream_t, int, int64_t, int, int, int, const T *, const T *, const T *, T *,
                           GradArgs, int *);
 int rowgemm_tile_cols(int N);
+int rowgemm_grid_y(int N);
 template <typename T>
 hipError_t launch_pcg_r(hipStream_t, int, int64_t, int, const T *, const uint8_t *, const double *, const double *,
                         const T *, const T *, T *, double *);
@@ -599,8 +600,7 @@ int gram(ofks_ctx *c, const T *X, const T *BX, const T *HX, std::vector<double> 
 
 size_t partials_needed(ofks_ctx *c, int p) {
     const GramPlan plan = gram_plan(c->n, p, 2048);
-    const int tc = rowgemm_tile_cols(2 * p);
-    const size_t gy = (2 * p + tc - 1) / tc;
+    const size_t gy = rowgemm_grid_y(2 * p);
     size_t need = (size_t)plan.splits * p * 2 * p;
     need = std::max(need, (size_t)c->gemm_rows * gy * (1 + p));
     need = std::max(need, (size_t)std::max(c->grid, c->shift_grid) * std::max(p, 5));
@@ -1019,8 +1019,7 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
     // G, R (kkt) and the start of the CG (paper) or the column norms of G (learned)
     int gx = 0;
     const int epi = (use_paper && any_active) ? EPI_GRAD_PCG : (use_learned ? EPI_GRAD_NORM : EPI_GRAD);
-    const int tc = rowgemm_tile_cols(2 * p);
-    const int gy = (2 * p + tc - 1) / tc;
+    const int gy = rowgemm_grid_y(2 * p);
     CHK(ensure_part(c, (size_t)c->gemm_rows * gy * (1 + p)));
     {
         // built after the partial buffer is final: it carries that pointer
