@@ -73,7 +73,8 @@ typedef struct {
     int32_t scf;            /* 1: rebuild H(X) every iteration (Kohn-Sham); 0: fixed H */
     int32_t energy_every;   /* evaluate the energy every k-th iteration (>= 1) */
     double refine_tol;      /* F32 only: switch to FP64 when rel < refine_tol, or when the FP32
-                               iterates have not lowered rel for 50 iterations (0: never switch) */
+                               iterates have not lowered rel for 50 iterations or not halved their
+                               lowest rel over the last 100 (0: never switch) */
     double poisson_rtol;    /* Hartree CG relative residual */
     int32_t poisson_max_iter;
     int32_t fallback_window;/* learned form: W iterations of energy history (<= 0: no fallback) */

@@ -1943,12 +1943,15 @@ int ofks_step(ofks_ctx *c, int32_t max_steps, ofks_iter_stats *stats, int32_t *n
         }
         if (c->prec == OFKS_F32 && c->prm.refine_tol > 0.0) {
             // switch to FP64 below refine_tol, or when the FP32 phase has not
-            // lowered its best residual for 50 iterations (its rounding floor)
+            // lowered its best residual for 50 iterations (its rounding floor),
+            // or has not halved it over the last 100 (a crawl near the floor)
             if (st.rel < c->f32_best) {
                 c->f32_best = st.rel;
                 c->f32_best_k = st.k;
             }
-            if (st.rel < c->prm.refine_tol || st.k - c->f32_best_k > 50) {
+            const int64_t nr = (int64_t)c->relmin.size();
+            const bool crawl = nr > 100 && c->relmin[nr - 1] > 0.5 * c->relmin[nr - 101];
+            if (st.rel < c->prm.refine_tol || st.k - c->f32_best_k > 50 || crawl) {
                 rc = promote_to_f64(c);
                 if (rc < 0) break;
             }
