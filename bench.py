@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-baseline", default="auto", choices=["auto", "skip"])
     ap.add_argument("--max-iter", type=int, default=1500)
+    ap.add_argument("--poisson-adapt", type=float, default=0.0,
+                    help="SCF workloads: Hartree CG tolerance max(1e-12, this x the previous residual) (0: 1e-12)")
     ap.add_argument("--energy-legs", default="both", choices=["both", "fp64", "mixed"],
                     help="which runs --energy-check makes (one per process for the largest workloads)")
     ap.add_argument("--energy-check", type=float, default=0.0,
@@ -397,7 +399,7 @@ def main():
     torch.cuda.synchronize()
     log(f"device assembly {time.perf_counter() - t:.2f}s nnz={s.nnz}")
     params = dict(beta=w.beta, precond="paper", pcg_iters=a.pcg_iters, max_iter=a.max_iter,
-                  scf=1 if w.scf else 0, energy_every=10 if p > 64 else 1)
+                  scf=1 if w.scf else 0, energy_every=10 if p > 64 else 1, poisson_adapt=a.poisson_adapt)
     s.set_params(tol=1e-30, **params)
     set_start(torch, s, X0)
     s.step(a.warmup)

@@ -91,6 +91,10 @@ typedef struct {
                                than the halo holds).  The kernels agree to rounding. */
     int32_t fallback_stall; /* learned forms: also fall back when the fallback_stall iterates before the
                                current one did not halve the lowest rel (<= 0: never; default 30) */
+    double poisson_adapt;   /* SCF: inside the iteration the Hartree CG stops at relative residual
+                               max(poisson_rtol, poisson_adapt x rel of the previous iterate), the
+                               first at max(poisson_rtol, poisson_adapt) (0, default: always poisson_rtol);
+                               the single-call density paths keep poisson_rtol */
 } ofks_params;
 
 typedef struct {

@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("algorithm", _c_int32),
         ("spmm_mode", _c_int32),
         ("fallback_stall", _c_int32),
+        ("poisson_adapt", _c_double),
     ]
 
 

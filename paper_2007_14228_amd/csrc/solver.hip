@@ -300,6 +300,7 @@ struct ofks_ctx {
     size_t lp_u_bytes = 0;
 
     double *scratch_dev = nullptr;   // this device's copy of `scratch` (ofks_gram_noalloc)
+    double poisson_tol_now = 0.0;    // > 0: the Hartree CG tolerance of the current iteration
     // caller-owned workspace (ofks_set_workspace): the iteration's device
     // state is carved from it in order while ws_carve is set
     char *ws_base = nullptr;
@@ -703,7 +704,8 @@ int poisson(ofks_ctx *c) {
     std::vector<double> sc;
     CHK(download(c, sc, c->cg_sc, 3));
     double rr = sc[1], bb = sc[2];
-    const double tol2 = c->prm.poisson_rtol * c->prm.poisson_rtol * bb;
+    const double rt = c->poisson_tol_now > 0.0 ? c->poisson_tol_now : c->prm.poisson_rtol;
+    const double tol2 = rt * rt * bb;
     // ten CG iterations (30 launches; an even count, so <r, z> ends in sc[0]
     // again), replayed as one graph when allowed
     auto chunk = [&](hipStream_t s) -> hipError_t {
@@ -749,7 +751,7 @@ int poisson(ofks_ctx *c) {
         rr = sc[1];
         if (!std::isfinite(rr)) return fail(c, OFKS_ENONFINITE, "Hartree CG diverged");
     }
-    if (rr > tol2) return fail(c, OFKS_NOT_CONVERGED, "Hartree CG did not reach %g", c->prm.poisson_rtol);
+    if (rr > tol2) return fail(c, OFKS_NOT_CONVERGED, "Hartree CG did not reach %g", rt);
     return OFKS_OK;
 }
 
@@ -890,7 +892,14 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
         }
         c->dinv_h = dn;
         CHK(upload<T>(c, B.dinv, dn));
-        CHK(build_h<T>(c, B.Xt, B.dinv));
+        // inexact Hartree solves while the iteration is far from converged
+        const double relp = (c->k > 0 && std::isfinite(c->last_rel)) ? c->last_rel : 1.0;
+        c->poisson_tol_now = c->prm.poisson_adapt > 0.0
+                                 ? std::max(c->prm.poisson_rtol, c->prm.poisson_adapt * relp)
+                                 : 0.0;
+        const int rc = build_h<T>(c, B.Xt, B.dinv);
+        c->poisson_tol_now = 0.0;
+        CHK(rc);
     }
 
     // HX~, BX~
@@ -1490,6 +1499,7 @@ void ofks_default_params(ofks_params *p) {
     p->use_graphs = 1;
     p->algorithm = 0;
     p->fallback_stall = 30;
+    p->poisson_adapt = 0.0;
 }
 
 int ofks_create(ofks_ctx **out, void *hip_stream) {
@@ -1776,7 +1786,7 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
         prm->precond < 0 || prm->precond > 3 || prm->step_rule < 0 || prm->step_rule > 4 ||
         (prm->precision != OFKS_F64 && prm->precision != OFKS_F32) || prm->fallback_rule < 0 ||
         prm->fallback_rule > 1 || prm->algorithm < 0 || prm->algorithm > 1 || prm->spmm_mode < 0 ||
-        prm->spmm_mode > 2)
+        prm->spmm_mode > 2 || !(prm->poisson_adapt >= 0.0) || !std::isfinite(prm->poisson_adapt))
         return fail(c, OFKS_EINVAL, "set_params: invalid parameter");
     if (prm->precond == OFKS_PRECOND_PAPER && prm->pcg_iters < 1)
         return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs pcg_iters >= 1");
