@@ -6,6 +6,8 @@
 #pragma once
 
 #include <cmath>
+#include <algorithm>
+#include <thread>
 #include <vector>
 
 namespace ofks {
@@ -13,32 +15,48 @@ namespace dense {
 
 // A = L L^T in place (lower triangle holds L, upper zeroed).  false if not SPD.
 inline bool cholesky(std::vector<double> &A, int p) {
+    // row-oriented dot products with four partial sums (their order is fixed)
+    auto dot = [](const double *x, const double *y, int m) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= m; k += 4) {
+            s0 += x[k] * y[k];
+            s1 += x[k + 1] * y[k + 1];
+            s2 += x[k + 2] * y[k + 2];
+            s3 += x[k + 3] * y[k + 3];
+        }
+        for (; k < m; ++k) s0 += x[k] * y[k];
+        return (s0 + s1) + (s2 + s3);
+    };
     for (int j = 0; j < p; ++j) {
-        double d = A[j * p + j];
-        for (int k = 0; k < j; ++k) d -= A[j * p + k] * A[j * p + k];
+        const double *aj = &A[(size_t)j * p];
+        double d = A[(size_t)j * p + j] - dot(aj, aj, j);
         if (!(d > 0.0) || !std::isfinite(d)) return false;
         d = std::sqrt(d);
-        A[j * p + j] = d;
+        A[(size_t)j * p + j] = d;
         for (int i = j + 1; i < p; ++i) {
-            double s = A[i * p + j];
-            for (int k = 0; k < j; ++k) s -= A[i * p + k] * A[j * p + k];
-            A[i * p + j] = s / d;
+            const double *ai = &A[(size_t)i * p];
+            A[(size_t)i * p + j] = (A[(size_t)i * p + j] - dot(ai, aj, j)) / d;
         }
-        for (int i = 0; i < j; ++i) A[i * p + j] = 0.0;
+        for (int i = 0; i < j; ++i) A[(size_t)i * p + j] = 0.0;
     }
     return true;
 }
 
-// inverse of a lower-triangular L (result lower triangular)
+// inverse of a lower-triangular L (result lower triangular), by rows:
+// row i of L^-1 is (e_i - sum_{k<i} L_ik row k) / L_ii
 inline std::vector<double> lower_inverse(const std::vector<double> &L, int p) {
-    std::vector<double> M(p * p, 0.0);
-    for (int j = 0; j < p; ++j) {
-        M[j * p + j] = 1.0 / L[j * p + j];
-        for (int i = j + 1; i < p; ++i) {
-            double s = 0.0;
-            for (int k = j; k < i; ++k) s += L[i * p + k] * M[k * p + j];
-            M[i * p + j] = -s / L[i * p + i];
+    std::vector<double> M((size_t)p * p, 0.0);
+    for (int i = 0; i < p; ++i) {
+        double *mi = &M[(size_t)i * p];
+        for (int k = 0; k < i; ++k) {
+            const double l = L[(size_t)i * p + k];
+            const double *mk = &M[(size_t)k * p];
+            for (int j = 0; j <= k; ++j) mi[j] -= l * mk[j];
         }
+        const double inv = 1.0 / L[(size_t)i * p + i];
+        for (int j = 0; j < i; ++j) mi[j] *= inv;
+        mi[i] = inv;
     }
     return M;
 }
@@ -140,22 +158,44 @@ inline bool sym_gen_eig(const std::vector<double> &A, const std::vector<double> 
 // tr(S^-1 A) for S SPD, via S = L L^T: sum_i (L^-1 A L^-T)_ii.
 inline bool trace_sinv_a(const std::vector<double> &S, const std::vector<double> &A, int p,
                          double &out) {
+    // S = L L^T, S^-1 A = L^-T (L^-1 A): tr(S^-1 A) = sum_i <row i of L^-1, row i of L^-1 A>.
+    // The rows are independent; from p = 256 on they are split over host
+    // threads, each row's term kept and the terms summed in row order.
     std::vector<double> L = S;
     if (!cholesky(L, p)) return false;
-    std::vector<double> Li = lower_inverse(L, p);
-    double tr = 0.0;
-    std::vector<double> t(p);
-    for (int i = 0; i < p; ++i) {
-        // t = row i of Li A
-        for (int j = 0; j < p; ++j) {
+    const std::vector<double> Li = lower_inverse(L, p);
+    std::vector<double> term(p);
+    auto rows = [&](int i0, int i1) {
+        std::vector<double> t(p);
+        for (int i = i0; i < i1; ++i) {
+            const double *li = &Li[(size_t)i * p];
+            for (int j = 0; j < p; ++j) t[j] = 0.0;
+            for (int k = 0; k <= i; ++k) {
+                const double l = li[k];
+                const double *a = &A[(size_t)k * p];
+                for (int j = 0; j < p; ++j) t[j] += l * a[j];
+            }
             double s = 0.0;
-            for (int k = 0; k <= i; ++k) s += Li[i * p + k] * A[k * p + j];
-            t[j] = s;
+            for (int k = 0; k <= i; ++k) s += t[k] * li[k];
+            term[i] = s;
         }
-        double s = 0.0;
-        for (int k = 0; k <= i; ++k) s += t[k] * Li[i * p + k];
-        tr += s;
+    };
+    const int nt = p >= 256 ? std::max(1, std::min(8, (int)std::thread::hardware_concurrency())) : 1;
+    if (nt == 1) {
+        rows(0, p);
+    } else {
+        // rows i cost ~ i: cut so that every thread gets about the same work
+        std::vector<std::thread> th;
+        int lo = 0;
+        for (int t = 0; t < nt; ++t) {
+            const int hi = t == nt - 1 ? p : (int)std::lround(p * std::sqrt((t + 1.0) / nt));
+            if (hi > lo) th.emplace_back(rows, lo, hi);
+            lo = std::max(lo, hi);
+        }
+        for (auto &x : th) x.join();
     }
+    double tr = 0.0;
+    for (int i = 0; i < p; ++i) tr += term[i];
     out = tr;
     return true;
 }

@@ -181,7 +181,7 @@ def test_halo_plan_under_sanitizers(tmp_path, graded):
             assert rc == 0 and rc2 == 0 and nb > 0, (name, rc, rc2, nb)
 
 
-@pytest.mark.parametrize("p", [1, 2, 7, 33, 64])
+@pytest.mark.parametrize("p", [1, 2, 7, 33, 64, 300])
 def test_dense_algebra_under_sanitizers(tmp_path, p):
     exe = _build(tmp_path, "dense.cpp", DENSE_DRIVER, ["g++", "-std=c++17", "-I", CSRC], [])
     rng = np.random.default_rng(p)
