@@ -392,8 +392,10 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
                     const T *__restrict__ M, T *__restrict__ Y, GradArgs ga) {
     constexpr int TR = 64, TC = 16 * NTW, KC = OFKS_RG_KC, TCB = TC * CT, NTH = 256 * CT;
     using acc_t = typename mfma4<T>::type;
-    __shared__ T As[TR][KC + 1];
-    __shared__ T Ms[KC][TCB];
+    // two LDS buffers: chunk f + 1 is stored into one while chunk f is read
+    // from the other, so a chunk needs one barrier instead of two
+    __shared__ T As[2][TR][KC + 1];
+    __shared__ T Ms[2][KC][TCB];
     __shared__ double red[NTH];
     // per-column epilogue constants of this block's columns, fixed for the
     // launch (in LDS rather than registers: it keeps more waves resident)
@@ -465,15 +467,20 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
             for (int j = 0; j < MR; ++j) mr[j] = (k < p && c0 + m_cc + j < N) ? M[(int64_t)k * N + c0 + m_cc + j] : T(0);
         }
     };
-    auto store_chunk = [&]() {
+    auto store_chunk = [&](int sb) {
         if (a_mover) {
 #pragma unroll
-            for (int j = 0; j < AR; ++j) As[a_rr][a_kk + j] = ar[j];
+            for (int j = 0; j < AR; ++j) As[sb][a_rr][a_kk + j] = ar[j];
         }
 #pragma unroll
-        for (int j = 0; j < MR; ++j) Ms[m_kk][m_cc + j] = mr[j];
+        for (int j = 0; j < MR; ++j) Ms[sb][m_kk][m_cc + j] = mr[j];
     };
-    if ((int64_t)blockIdx.x < ntiles) load_chunk(blockIdx.x, 0);
+    int buf = 0;
+    if ((int64_t)blockIdx.x < ntiles) {
+        load_chunk(blockIdx.x, 0);
+        store_chunk(0);
+    }
+    __syncthreads();
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * TR;
@@ -481,18 +488,19 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
 #pragma unroll
         for (int t = 0; t < NTW; ++t) acc[t] = acc_t{T(0), T(0), T(0), T(0)};
         for (int k0 = 0; k0 < p; k0 += KC) {
-            store_chunk();
-            __syncthreads();
             const bool last = k0 + KC >= p;
             const int64_t nt = last ? tile + gridDim.x : tile;
-            if (nt < ntiles) load_chunk(nt, last ? 0 : k0 + KC);
+            const bool more = nt < ntiles;
+            if (more) load_chunk(nt, last ? 0 : k0 + KC);
 #pragma unroll
             for (int s4 = 0; s4 < KC / 4; ++s4) {
-                const T a = As[16 * wr + li][4 * s4 + lk];
+                const T a = As[buf][16 * wr + li][4 * s4 + lk];
 #pragma unroll
-                for (int t = 0; t < NTW; ++t) acc[t] = mfma16x16x4(a, Ms[4 * s4 + lk][cw + 16 * t + li], acc[t]);
+                for (int t = 0; t < NTW; ++t) acc[t] = mfma16x16x4(a, Ms[buf][4 * s4 + lk][cw + 16 * t + li], acc[t]);
             }
+            if (more) store_chunk(buf ^ 1);   // last read in the previous chunk, before its barrier
             __syncthreads();
+            buf ^= 1;
         }
         // epilogue: lane holds rows r0 + 16 wr + mfma_row(lk, i) of column c0 + cw + 16 t + li
 #pragma unroll
