@@ -87,10 +87,17 @@ def _forward(W, norm, Lh, Bm, hd, lam, G):
     return dict(fs=fs, ft=ft, h=h, x=x, J=J, Ts=Ts, Z=Z, R=R, P=P)
 
 
-def apply(W, norm, Lh, Bm, hd, lam, G):
+def apply(W, norm, Lh, Bm, hd, lam, G, sweeps: int = 1):
     """P for the block G (n x p); Lh = L/2 and Bm = B as scipy sparse
-    matrices, hd the diagonal of H."""
-    return _forward(W, norm, Lh, Bm, hd, lam, G)["P"]
+    matrices, hd the diagonal of H.  sweeps > 1 repeats the damped sweep
+    with the same weights, P <- P + ft J (G - T P): a fixed polynomial in
+    J T applied to G, which for 0 < ft J T < 2 tends to T^-1 G (the
+    preconditioner of eq. precondition-T) as the sweeps grow."""
+    f = _forward(W, norm, Lh, Bm, hd, lam, G)
+    P = f["P"]
+    for _ in range(sweeps - 1):
+        P = P + f["ft"] * f["J"] * (G - _apply_T(f["Ts"], P))
+    return P
 
 
 def loss_grad(W, norm, Lh, Bm, hd, lam, G):

@@ -54,6 +54,7 @@ class Params:
     step_rule: str = "bb2"         # "bb2" | "bb1" | "abb1" | "abb2" | "fixed"
     precond_lambda: str = "lambda2"
     lp_weights: object = None      # learned form: (W[193], norm[8]); graph form: (W[226], norm[8])
+    graph_sweeps: int = 1          # graph form: damped sweeps through T (the first after the heads)
     fallback_window: int = 5
     fallback_hold: int = 20
     fallback_rule: str = "min"     # fall back when E^k exceeds the "min" or "max" of the window
@@ -158,7 +159,8 @@ def precondition(prob, G, lam_diag, params: Params, kind: str = None):
         from . import gnn
         W, norm = params.lp_weights
         mat = lambda v: sp.csr_matrix((v, prob.col, prob.row_ptr), shape=(prob.n, prob.n))
-        return gnn.apply(W, norm, mat(prob.Lhval), mat(prob.Bval), prob.diag(prob.Hval), lam_diag, G)
+        return gnn.apply(W, norm, mat(prob.Lhval), mat(prob.Bval), prob.diag(prob.Hval), lam_diag, G,
+                         sweeps=params.graph_sweeps)
     if kind != "paper":
         raise ValueError(kind)
     neg = lam_diag < 0

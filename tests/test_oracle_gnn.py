@@ -111,3 +111,40 @@ def test_gnn_gradient_step_lowers_the_loss(c1):
     loss, g = gnn.loss_grad(W, norm, Lh, Bm, hd, LAM, G)
     step = 1e-3 / max(1.0, float(np.linalg.norm(g)))
     assert gnn.loss_grad(W - step * g, norm, Lh, Bm, hd, LAM, G)[0] < loss
+
+
+def test_gnn_sweeps_converge_to_the_solve_of_T(c1):
+    """Repeated damped sweeps with fixed heads (fs = 0, ft = 0.65) are
+    Richardson iteration on T_l x = g_l with the Jacobi weights, P_m -> T_l^-1
+    g_l (eq. precondition-T): the T-norm error falls with every doubling of
+    the sweeps and reaches rounding (a direct solve by scipy is the
+    reference); identity-branch columns stay g_l.  Two sweeps equal the
+    recurrence written out with scipy matrices."""
+    Lh, Bm, hd, G = c1
+    W = gnn.init_weights(0)
+    W[5 * gnn.H:] = 0.0
+    W[-1] = 0.65                         # b2 = (fs, ft) = (0, 0.65)
+    norm = _norm()
+    Ts = [(Lh - l * Bm).tocsc() for l in LAM]
+    X = np.column_stack([spla.spsolve(Ts[i], G[:, i]) if l < 0 else G[:, i] for i, l in enumerate(LAM)])
+    J = mlp.jacobi(Lh.diagonal(), Bm.diagonal(), LAM)
+
+    def tnorm_err(P):
+        return [float(np.sqrt((P[:, i] - X[:, i]) @ (Ts[i] @ (P[:, i] - X[:, i])))) for i in (0, 2)]
+
+    prev = None
+    for m in (1, 2, 4, 16, 64, 256):
+        P = gnn.apply(W, norm, Lh, Bm, hd, LAM, G, sweeps=m)
+        assert np.array_equal(P[:, 1], G[:, 1])
+        e = tnorm_err(P)
+        if prev is not None:
+            assert all(a < b for a, b in zip(e, prev)) or max(e) < 1e-12 * np.abs(X).max()
+        prev = e
+    ref = [float(np.sqrt(X[:, i] @ (Ts[i] @ X[:, i]))) for i in (0, 2)]
+    assert all(a < 1e-12 * r for a, r in zip(prev, ref))
+    # two sweeps written out
+    P1 = J * G + 0.65 * J * (G - np.column_stack([Ts[i] @ (J[:, i] * G[:, i]) if l < 0 else J[:, i] * G[:, i]
+                                                   for i, l in enumerate(LAM)]))
+    TP1 = np.column_stack([Ts[i] @ P1[:, i] if l < 0 else P1[:, i] for i, l in enumerate(LAM)])
+    P2 = P1 + 0.65 * J * (G - TP1)
+    assert np.allclose(gnn.apply(W, norm, Lh, Bm, hd, LAM, G, sweeps=2), P2, rtol=1e-13, atol=1e-13)
