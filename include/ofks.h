@@ -95,6 +95,9 @@ typedef struct {
                                max(poisson_rtol, poisson_adapt x rel of the previous iterate), the
                                first at max(poisson_rtol, poisson_adapt) (0, default: always poisson_rtol);
                                the single-call density paths keep poisson_rtol */
+    int32_t graph_sweeps;   /* graph form: damped sweeps through T_l per application (1..64, default 1):
+                               the first after the heads, each further one P <- P + ft J (G - T P) with
+                               the same weights (one shifted SpMM each); training covers one sweep */
 } ofks_params;
 
 typedef struct {

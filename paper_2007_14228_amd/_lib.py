@@ -42,6 +42,7 @@ class Params(ctypes.Structure):
         ("spmm_mode", _c_int32),
         ("fallback_stall", _c_int32),
         ("poisson_adapt", _c_double),
+        ("graph_sweeps", _c_int32),
     ]
 
 

@@ -1147,11 +1147,19 @@ template <typename T> int iterate(ofks_ctx *c, ofks_iter_stats *st, bool *stop) 
             HIPCHK(launch_gl_heads<T>(c->stream, n, p, B.P, c->lhd, c->bd, c->hd, B.lam, c->active, c->g2, c->gl_W,
                                       c->gl_norm, B.D, c->gl_ft));
         }
-        int used = 0;
-        CHK(spmm_shift<T>(c, p, lbT<T>(c), B.lam, c->active, B.D, B.HX, &used));
-        Scope sc(c, "graph");
-        HIPCHK(launch_gl_out<T>(c->stream, n, p, B.P, B.D, c->gl_ft, B.HX, c->lhd, c->bd, B.lam, c->active, B.P,
-                                (T *)nullptr));
+        // sweep s: P_s = P_{s-1} + ft J (G - T P_{s-1}), P_0 = Z; G stays in P
+        // until the last sweep writes there; the others alternate R and D
+        const int m = std::max(1, c->prm.graph_sweeps);
+        T *src = B.D;
+        for (int sw = 1; sw <= m; ++sw) {
+            int used = 0;
+            CHK(spmm_shift<T>(c, p, lbT<T>(c), B.lam, c->active, src, B.HX, &used));
+            T *dst = sw == m ? B.P : (src == B.R ? B.D : B.R);
+            Scope sc(c, "graph");
+            HIPCHK(launch_gl_out<T>(c->stream, n, p, B.P, src, c->gl_ft, B.HX, c->lhd, c->bd, B.lam, c->active, dst,
+                                    (T *)nullptr));
+            src = dst;
+        }
     } else if (use_learned) {
         if (!c->lp_ready) return fail(c, OFKS_ESTATE, "learned preconditioner: no weights (ofks_lp_set_weights)");
         HIPCHK(hipMemcpyAsync(c->g2, c->red + 1, p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1500,6 +1508,7 @@ void ofks_default_params(ofks_params *p) {
     p->algorithm = 0;
     p->fallback_stall = 30;
     p->poisson_adapt = 0.0;
+    p->graph_sweeps = 1;
 }
 
 int ofks_create(ofks_ctx **out, void *hip_stream) {
@@ -1786,7 +1795,8 @@ int ofks_set_params(ofks_ctx *c, const ofks_params *prm) {
         prm->precond < 0 || prm->precond > 3 || prm->step_rule < 0 || prm->step_rule > 4 ||
         (prm->precision != OFKS_F64 && prm->precision != OFKS_F32) || prm->fallback_rule < 0 ||
         prm->fallback_rule > 1 || prm->algorithm < 0 || prm->algorithm > 1 || prm->spmm_mode < 0 ||
-        prm->spmm_mode > 2 || !(prm->poisson_adapt >= 0.0) || !std::isfinite(prm->poisson_adapt))
+        prm->spmm_mode > 2 || !(prm->poisson_adapt >= 0.0) || !std::isfinite(prm->poisson_adapt) ||
+        prm->graph_sweeps < 1 || prm->graph_sweeps > 64)
         return fail(c, OFKS_EINVAL, "set_params: invalid parameter");
     if (prm->precond == OFKS_PRECOND_PAPER && prm->pcg_iters < 1)
         return fail(c, OFKS_EINVAL, "set_params: the paper preconditioner needs pcg_iters >= 1");

@@ -233,3 +233,35 @@ def test_stalled_learned_form_falls_back_on_the_gpu(c1):
     ref = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p]
     assert abs(st[-1]["energy"] - sum(ref)) < 1e-8 * abs(sum(ref))
     s.close()
+
+
+@pytest.mark.parametrize("mode", ["gather", "halo"])
+def test_graph_sweeps_follow_the_oracle(mode, c1):
+    """Three damped sweeps per application (the library's graph_sweeps): the
+    first iterations against the oracle's (fallbacks off), FP64 blocks, kkt to
+    1e-5 (the network is FP32); then, fallbacks on, convergence to the dense
+    eigenvalues."""
+    w, d = c1
+    print(f"[gpu] graph sweeps=3 {mode}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    W = _weights(13)
+    X0 = pcal.chol_gs(prob, wl.random_block(3, d.n, w.p))
+    off = dict(fallback_window=0, fallback_stall=0)
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=5, precond="graph",
+                                              lp_weights=(W, NORM), graph_sweeps=3, **off))
+    s = _solver(w)
+    s.gl_set_weights(W, NORM)
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=5, precond="graph", spmm_mode=mode, energy_every=1,
+                 graph_sweeps=3, **off)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, _, _ = s.step(6)
+    assert len(st) == len(hist) == 6
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-5 * b.kkt, (a, b)
+    s.set_params(beta=w.beta, tol=1e-10, max_iter=3000, precond="graph", spmm_mode=mode, graph_sweeps=3)
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, done, _ = s.step(3000)
+    assert done and st[-1]["rel"] < 1e-10
+    ref = json.load(open(os.path.join(GOLDEN, "c1_dense_eigs.json")))["eigenvalues"][: w.p]
+    assert abs(st[-1]["energy"] - sum(ref)) < 1e-9 * abs(sum(ref))
+    s.close()
