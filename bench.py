@@ -177,6 +177,11 @@ def learned_legs(torch, s, X0, mparams):
     legs["mixed_graph_form_untrained"] = run_to_tol(torch, s, X0, 1e-6, dict(mparams, precond="graph",
                                                                              energy_every=1))
     log(f"  {legs['mixed_graph_form_untrained']}")
+    log("time to residual 1e-6: mixed precision + graph form, fixed heads, five sweeps, no fallback")
+    legs["mixed_graph_5_sweeps_alone"] = run_to_tol(torch, s, X0, 1e-6, dict(mparams, precond="graph", energy_every=1,
+                                                                             graph_sweeps=5, fallback_window=0,
+                                                                             fallback_stall=0))
+    log(f"  {legs['mixed_graph_5_sweeps_alone']}")
     return legs
 
 
