@@ -15,9 +15,12 @@
  *    that return host values synchronize that stream only.
  *  - "host" pointers are read or written during the call only; "device"
  *    pointers are caller-owned device memory that must stay valid during the
- *    call.  The library owns the device memory it allocates for its state;
- *    it allocates only in setup calls (mesh load, assemble, csr load, set_x0,
- *    precision switch) and frees it in ofks_destroy.
+ *    call.  The library owns the device memory it allocates for its state:
+ *    the system in the setup calls (mesh load, assemble, csr load), the
+ *    iteration's state in set_x0 and, lazily, in the first steps (the rest
+ *    of the FP64 blocks, the precision switch, SCF and graph-form arrays),
+ *    all freed in ofks_destroy.  With a caller workspace (ofks_set_workspace)
+ *    the iteration's state is carved from it instead.
  *  - Blocks X (n x p) are row-major: the p values of one DOF are contiguous.
  *    n counts interior (non-Dirichlet) nodes, numbered in node order.
  *  - CSR matrices: row_ptr int64[n+1], col int32[nnz], columns sorted
@@ -44,7 +47,7 @@ enum {
     OFKS_EINVAL = -1,         /* bad argument */
     OFKS_ESTATE = -2,         /* call out of order */
     OFKS_EHIP = -3,           /* HIP runtime error */
-    OFKS_ECAPACITY = -4,      /* mesh exceeds a compiled-in bound */
+    OFKS_ECAPACITY = -4,      /* a compiled-in bound (mesh, no-allocation scratch) or the caller's workspace is exceeded */
     OFKS_ENONFINITE = -5,     /* NaN/Inf in a p x p quantity */
     OFKS_ENOTSPD = -6,        /* Gram matrix not positive definite */
     OFKS_EZERONORM = -7,      /* a column with zero B-norm */
