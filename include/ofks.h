@@ -211,6 +211,10 @@ int ofks_energy(ofks_ctx *ctx, double *parts);
 int ofks_postprocess(ofks_ctx *ctx, double *eigs);
 
 /* Current normalized iterate X^k into dev_X (device f64[n*p]). */
+/* The current iterate's block width p, the precision of its blocks
+ * (OFKS_F64 / OFKS_F32) and its iteration index k (any pointer may be NULL).
+ * ESTATE before ofks_set_x0 or ofks_state_set. */
+int ofks_iterate_info(ofks_ctx *ctx, int32_t *p, int32_t *precision, int32_t *k);
 int ofks_get_x(ofks_ctx *ctx, double *dev_X);
 
 /* SCF: density rho at the 4 quadrature points of every tetrahedron of the

@@ -74,6 +74,7 @@ SIGNATURES = [
     ("ofks_nuclei_set", I32, [P, I32, P, P]),
     ("ofks_assemble", I32, [P]),
     ("ofks_csr_info", I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+    ("ofks_iterate_info", I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     ("ofks_csr_get", I32, [P, P, P, P, P, P]),
     ("ofks_csr_load", I32, [P, I64, I64, P, P, P, P, P]),
     ("ofks_set_params", I32, [P, ctypes.POINTER(Params)]),

@@ -2024,6 +2024,14 @@ int ofks_energy(ofks_ctx *c, double *parts) {
     return OFKS_OK;
 }
 
+int ofks_iterate_info(ofks_ctx *c, int32_t *p, int32_t *precision, int32_t *k) {
+    CHK(check_ready(c));
+    if (p) *p = c->p;
+    if (precision) *precision = c->prec;
+    if (k) *k = (int32_t)c->k;
+    return OFKS_OK;
+}
+
 int ofks_get_x(ofks_ctx *c, double *dev_X) {
     CHK(check_ready(c));
     if (!dev_X) return fail(c, OFKS_EINVAL, "get_x: null output");

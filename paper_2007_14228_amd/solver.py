@@ -247,6 +247,13 @@ class Solver:
         if not buf.is_cuda or buf.dtype != __import__("torch").uint8 or not buf.is_contiguous():
             raise TypeError("state must be a contiguous device uint8 tensor")
         self._check(self.lib.ofks_state_set(self.h, ctypes.c_void_p(buf.data_ptr()), int(buf.numel())))
+        self.p = self.iterate_info()[0]
+
+    def iterate_info(self):
+        """(p, precision, k) of the current iterate."""
+        p, prec, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.ofks_iterate_info(self.h, ctypes.byref(p), ctypes.byref(prec), ctypes.byref(k)))
+        return p.value, prec.value, k.value
 
     # -- single kernels -------------------------------------------------------
     def spmm(self, X):

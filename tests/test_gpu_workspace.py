@@ -96,3 +96,41 @@ def test_workspace_run_equals_library_run(case):
     for x, y in zip(again, ref):
         assert _same(x["kkt"], y["kkt"])
     s.close()
+
+
+@pytest.mark.parametrize("case", ["fp64", "mixed"])
+def test_resume_into_a_workspace(case):
+    """ofks_state_set on a context whose iteration state lives in a caller
+    workspace: the resumed steps equal the uninterrupted run's bit for bit
+    (FP64, and across the FP32 -> FP64 switch, whose FP64 set then comes from
+    the region the workspace keeps for it)."""
+    import torch
+    from paper_2007_14228_amd import Solver
+    cfg = dict(CASES[case])
+    w = wl.make_workload("c1")
+    print(f"[gpu] workspace resume {case}", flush=True)
+    prm = dict(beta=w.beta, tol=1e-30, max_iter=500, pcg_iters=10, energy_every=1, **cfg["params"])
+    k1, k2 = (5, 12) if case == "fp64" else (4, 50)
+    a = Solver()
+    a.load_workload(w)
+    a.set_params(**prm)
+    a.set_x0(_dev(wl.random_block(4, w.mesh.n_dofs, w.p)), orthonormalize=True)
+    a.step(k1)
+    state = a.state_get()
+    ref, _, _ = a.step(k2)
+    xa = a.get_x().cpu().numpy()
+    b = Solver()
+    b.load_workload(w)
+    b.set_params(**prm)
+    ws = torch.zeros(b.workspace_size(w.p), dtype=torch.uint8, device="cuda")
+    b.set_workspace(ws)
+    b.state_set(state)
+    got, _, _ = b.step(k2)
+    for x, y in zip(got, ref):
+        for f in FIELDS:
+            assert _same(x[f], y[f]), (case, f, x, y)
+    assert np.array_equal(b.get_x().cpu().numpy(), xa)
+    if case == "mixed":
+        assert ref[0]["precision"] == 1 and ref[-1]["precision"] == 0
+    a.close()
+    b.close()
