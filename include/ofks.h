@@ -97,7 +97,8 @@ typedef struct {
     double poisson_adapt;   /* SCF: inside the iteration the Hartree CG stops at relative residual
                                max(poisson_rtol, poisson_adapt x rel of the previous iterate), the
                                first at max(poisson_rtol, poisson_adapt) (0, default: always poisson_rtol);
-                               the single-call density paths keep poisson_rtol */
+                               the single-call density paths keep poisson_rtol.  1e-3 is safe on the
+                               meshes measured; 1e-2 can stall the last decade */
     int32_t graph_sweeps;   /* graph form: damped sweeps through T_l per application (1..64, default 1):
                                the first after the heads, each further one P <- P + ft J (G - T P) with
                                the same weights (one shifted SpMM each); training covers one sweep */
