@@ -370,9 +370,10 @@ def unstructured_mesh(half: float, Z, R, gamma1: float, gamma2: float, hmin: flo
 
 
 def unstructured_mesh_for_dofs(half: float, Z, R, target_dofs: int, gamma2: float, hmin: float,
-                               seed: int = 0, iters: int = 30, progress=None) -> tuple:
+                               seed: int = 0, iters: int = 30, progress=None, **mesh_kw) -> tuple:
     """Bisection on gamma1 so that the interior node count of the octree
-    lattice is close to target_dofs, then unstructured_mesh."""
+    lattice is close to target_dofs, then unstructured_mesh (mesh_kw: its
+    jitter, qmin, rounds)."""
 
     def dofs(g1):
         P, _, _, nmax = octree_lattice(half, Z, R, g1, gamma2, hmin)
@@ -388,7 +389,7 @@ def unstructured_mesh_for_dofs(half: float, Z, R, target_dofs: int, gamma2: floa
     g1 = lo if abs(dofs(lo) - target_dofs) <= abs(dofs(hi) - target_dofs) else hi
     if progress:
         progress(f"mesh-size law: gamma1 = {g1:.4g}")
-    return unstructured_mesh(half, Z, R, g1, gamma2, hmin, seed=seed, progress=progress), g1
+    return unstructured_mesh(half, Z, R, g1, gamma2, hmin, seed=seed, progress=progress, **mesh_kw), g1
 
 
 # ----------------------------------------------------------------------------
