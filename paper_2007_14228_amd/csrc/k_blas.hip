@@ -581,6 +581,210 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
 }
 
 // ---------------------------------------------------------------------------
+// The gradient row GEMM with the multiplier resident in LDS (p = 64 or 128,
+// N = 2p, K = p).  The block stages its TCB = 16 NT output columns of
+// diag(sa) M once, for all K (135 KB for FP64 at p = 128, where each block
+// holds one of the two 128-column halves; FP32 and p = 64 hold all N
+// columns).  Each wave then owns whole 16-row tiles, with no barrier in its
+// loop, so that the two waves of a SIMD drift apart and one's loads and
+// epilogue overlap the other's MFMAs.  Per tile, a wave:
+//  - issues the tile's HX (and diagonal) loads, which land during its MFMAs;
+//  - runs KG x 4 x NT MFMAs on the A rows it holds in registers (16-byte
+//    loads, lane (li, lk) holding k = 16 j + 4 lk + m, m < 4), with B read
+//    from LDS at the same k;
+//  - runs the epilogue, then issues the next tile's A loads.
+// Scheduling barriers keep the LDS reads of one (j, m) step from being
+// hoisted above the previous step: all in flight at once would not fit the
+// registers.  The column sums (PCG start, column norms) are reduced over the
+// wave after each tile and kept per wave in LDS, the residual sum per
+// thread in LDS, so neither holds registers through the MFMAs.
+// With two halves, blocks b and b + 8 (one XCD) take the two halves of the
+// same row tiles in the same order, so the second read of A and HX mostly
+// hits that XCD's L2.  The K order inside one MFMA is permuted (any order
+// of the 4 k values of an instruction gives the same sum up to rounding).
+// LDS layout of the staged multiplier: element (k, c) at
+// (k / 4) KS + (k % 4) TCB + c, with the k/4 stride padded by 16 values so
+// that the four lane groups lk of one read fall on different banks.
+// Partial sums per block as in k_rowgemm_mfma (one grid row).
+// ---------------------------------------------------------------------------
+template <typename T, int NT, int KG, int HALVES, int EPI>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+void k_rowgemm_mres(int64_t n, const T *__restrict__ A, const T *__restrict__ sa, const T *__restrict__ M,
+                    GradArgs ga) {
+    constexpr int P = 16 * KG, N = 2 * P, TCB = 16 * NT, VW = 16 / (int)sizeof(T), KS = 4 * TCB + 16;
+    static_assert(TCB * HALVES == N, "column split");
+    using acc_t = typename mfma4<T>::type;
+    __shared__ T Ms[4 * KG * KS];
+    __shared__ T scl_s[TCB], lmc_s[TCB];
+    __shared__ uint8_t act_s[TCB];
+    __shared__ double red[512];
+    // per wave and column: sum over its tiles of the epilogue's column sums
+    __shared__ double rzs[8][NT][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = blockIdx.x;
+    const int h = HALVES == 2 ? (b >> 3) & 1 : 0;
+    const int64_t q = HALVES == 2 ? (int64_t)(((b >> 4) << 3) | (b & 7)) : (int64_t)b;
+    const int64_t nq = HALVES == 2 ? gridDim.x / 2 : gridDim.x;
+    const int c0 = h * TCB;
+
+    // diag(sa) M, columns c0 .. c0 + TCB - 1, all P rows
+    for (int e = threadIdx.x; e < P * TCB; e += 512) {
+        const int k = e / TCB, c = e - k * TCB;
+        Ms[(k >> 2) * KS + (k & 3) * TCB + c] = sa[k] * M[k * N + c0 + c];
+    }
+    for (int cl = threadIdx.x; cl < TCB; cl += 512) {
+        const int c = c0 + cl;
+        const int cc = c < P ? c : c - P;
+        scl_s[cl] = sa[cc];
+        lmc_s[cl] = (EPI == EPI_GRAD_PCG && c < P) ? ((const T *)ga.lam)[c] : T(0);
+        act_s[cl] = (EPI == EPI_GRAD_PCG && c < P) ? ga.active[c] : 0;
+    }
+    __syncthreads();
+    const T *__restrict__ HX = (const T *)ga.HX;
+    T *__restrict__ Pout = (T *)ga.P;
+    T *__restrict__ Rout = (T *)ga.R;
+    T *__restrict__ Dout = (T *)ga.D;
+    // columns of this block below P (gradient) or at and above P (residual):
+    // per tile t, known at compile time with one column set, per block with two
+    const bool low_half = HALVES == 2 ? h == 0 : true;
+    auto is_grad = [&](int t) __attribute__((always_inline)) {
+        return HALVES == 2 ? low_half : (16 * t < P);
+    };
+    // HX column (and output column, below P) of tile t, less li
+    auto hcol = [](int t) __attribute__((always_inline)) {
+        return HALVES == 2 ? 16 * t : (16 * t < P ? 16 * t : 16 * t - P);
+    };
+
+    red[threadIdx.x] = 0.0;   // this thread's running sum of squared residual entries
+    if (lk == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) rzs[w][t][li] = 0.0;
+    }
+    T a[KG][4];
+    // rows past n read row n - 1 (their results are dropped)
+    auto load_a = [&](int64_t wt) __attribute__((always_inline)) {
+        int64_t r = wt * 16 + li;
+        if (r > n - 1) r = n - 1;
+        const T *src = A + r * P + 4 * lk;
+#pragma unroll
+        for (int j = 0; j < KG; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; v += VW)
+                load_vec<T, VW>(src + 16 * j + v, *reinterpret_cast<T(*)[VW]>(&a[j][v]));
+    };
+    const int64_t nwt = (n + 15) / 16;
+    const int64_t stride = nq * 8;
+    int64_t wt = q * 8 + w;
+    if (wt < nwt) load_a(wt);
+    for (; wt < nwt; wt += stride) {
+        // this tile's HX values (and diagonals), in flight during the MFMAs
+        // (lane l holds the diagonals of row l % 16; the epilogue shuffles)
+        T hx[4][NT];
+        double ldl = 0.0, bdl = 0.0;
+        if (EPI == EPI_GRAD_PCG) {
+            int64_t r = wt * 16 + li;
+            if (r > n - 1) r = n - 1;
+            ldl = ga.lhd[r];
+            bdl = ga.bd[r];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int64_t r = wt * 16 + mfma_row<T>(lk, i);
+            if (r > n - 1) r = n - 1;
+            const T *hrow = HX + r * P + li;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) hx[i][t] = hrow[hcol(t)];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        acc_t acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = acc_t{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < KG; ++j)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const T *mrow = Ms + (4 * j + lk) * KS + m * TCB + li;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(a[j][m], mrow[16 * t], acc[t]);
+                // keeps the LDS reads of later steps from being hoisted here
+                // (all of them in flight at once would not fit the registers)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        // epilogue: lane holds rows 16 wt + mfma_row(lk, i) of columns c0 + 16 t + li
+        double rz[NT], r2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) rz[t] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = wt * 16 + mfma_row<T>(lk, i);
+            T ldi = T(0), bdi = T(0);
+            if (EPI == EPI_GRAD_PCG) {   // all lanes take part in the shuffles
+                ldi = T(__shfl(ldl, mfma_row<T>(lk, i)));
+                bdi = T(__shfl(bdl, mfma_row<T>(lk, i)));
+            }
+            if (r >= n) continue;
+            T *prow = Pout + r * P + li;
+            T *rrow = Rout + r * P + li;
+            T *drow = Dout + r * P + li;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int cl = 16 * t + li;
+                const int hc = hcol(t);
+                const T v = fma(hx[i][t], scl_s[cl], acc[t][i]);
+                if (!is_grad(t)) {
+                    r2 += (double)v * (double)v;
+                } else if (EPI == EPI_GRAD) {
+                    prow[hc] = v;
+                } else if (EPI == EPI_GRAD_NORM) {
+                    prow[hc] = v;
+                    rz[t] += (double)v * (double)v;
+                } else {  // EPI_GRAD_PCG
+                    if (act_s[cl]) {
+                        const T z = v * (T(1) / (ldi - lmc_s[cl] * bdi));
+                        rrow[hc] = v;
+                        drow[hc] = z;
+                        rz[t] += (double)v * (double)z;
+                    } else {
+                        prow[hc] = v;
+                    }
+                }
+            }
+        }
+        red[threadIdx.x] += r2;
+        if (EPI == EPI_GRAD_PCG || EPI == EPI_GRAD_NORM) {
+            // the 4 lane groups' sums of each column, then this wave's running sum
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double v = rz[t];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (lk == 0) rzs[w][t][li] += v;
+            }
+        }
+        if (wt + stride < nwt) load_a(wt + stride);
+    }
+    double *part = ga.part + (int64_t)blockIdx.x * (1 + P);
+    __syncthreads();
+    for (int s = 256; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[0] = red[0];
+    __syncthreads();
+    if (EPI == EPI_GRAD_PCG || EPI == EPI_GRAD_NORM) {
+        for (int c = threadIdx.x; c < P; c += 512)
+            if (c < c0 || c >= c0 + TCB) part[1 + c] = 0.0;
+        for (int cl = threadIdx.x; cl < TCB; cl += 512) {
+            const int c = c0 + cl;
+            double sum = 0.0;
+            for (int ww = 0; ww < 8; ++ww) sum += rzs[ww][cl >> 4][cl & 15];
+            if (c < P) part[1 + c] = sum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Lane-per-column-slice kernels over n x p blocks (same mapping as SpMM).
 // ---------------------------------------------------------------------------
 
@@ -978,10 +1182,62 @@ int rowgemm_grid_y(int N) {
     return (N + w - 1) / w;
 }
 
+// The LDS-resident-multiplier row GEMM (gradient epilogues, N = 2p, p = 64 or
+// 128, 16-byte aligned A).  Off with -DOFKS_RG_MRES=0.
+#ifndef OFKS_RG_MRES
+#define OFKS_RG_MRES 1
+#endif
+// FP32 blocks at p = 128: 0 the chunked kernel, 1 all 256 columns per block,
+// 2 two 128-column halves
+#ifndef OFKS_RG_MRES_F32
+#define OFKS_RG_MRES_F32 1
+#endif
+template <typename T, int NT, int KG, int HALVES, int EPI>
+static int mres_grid(int cap) {
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rowgemm_mres<T, NT, KG, HALVES, EPI>, 512, 0);
+        cached = cus * (per > 0 ? per : 1);
+    }
+    int g = cached < cap ? cached : cap;
+    return g / 16 * 16;   // whole pairs of 8-block XCD groups (the two halves)
+}
+
+template <typename T, int NT, int KG, int HALVES>
+static hipError_t launch_mres(hipStream_t s, int epi, int64_t n, int cap, const T *A, const T *sa, const T *M,
+                              GradArgs ga, int *gx_out) {
+#define OFKS_MRES(E_)                                                                         \
+    if (epi == E_) {                                                                          \
+        const int g = mres_grid<T, NT, KG, HALVES, E_>(cap);                                  \
+        if (g < 16) return hipErrorInvalidValue;                                              \
+        if (gx_out) *gx_out = g;                                                              \
+        hipLaunchKernelGGL((k_rowgemm_mres<T, NT, KG, HALVES, E_>), dim3(g), dim3(512), 0, s, n, A, sa, M, ga); \
+        return hipGetLastError();                                                             \
+    }
+    OFKS_MRES(EPI_GRAD)
+    OFKS_MRES(EPI_GRAD_NORM)
+    OFKS_MRES(EPI_GRAD_PCG)
+#undef OFKS_MRES
+    return hipErrorInvalidValue;
+}
+
 // number of blocks along rows for k_rowgemm epilogues (fixed => deterministic)
 template <typename T>
 hipError_t launch_rowgemm(hipStream_t s, int epi, int64_t n, int p, int N, int grid_rows, const T *A,
                           const T *sa, const T *M, T *Y, GradArgs ga, int *gx_out) {
+    if (OFKS_RG_MRES && epi != EPI_PLAIN && N == 2 * p && (p == 64 || p == 128) && n > 0 &&
+        !(sizeof(T) == 4 && p == 128 && OFKS_RG_MRES_F32 == 0) &&
+        rowgemm_grid_y(N) == 1 && grid_rows >= 16 && reinterpret_cast<uintptr_t>(A) % 16 == 0) {
+        if (p == 128) {
+            if constexpr (sizeof(T) == 8) return launch_mres<T, 8, 8, 2>(s, epi, n, grid_rows, A, sa, M, ga, gx_out);
+            else if (OFKS_RG_MRES_F32 == 2) return launch_mres<T, 8, 8, 2>(s, epi, n, grid_rows, A, sa, M, ga, gx_out);
+            else if (OFKS_RG_MRES_F32 == 1) return launch_mres<T, 16, 8, 1>(s, epi, n, grid_rows, A, sa, M, ga, gx_out);
+        }
+        return launch_mres<T, 8, 4, 1>(s, epi, n, grid_rows, A, sa, M, ga, gx_out);
+    }
     const int tc = rowgemm_tile_cols(N);
     const int nt = tc / 16;
     const int mt = 4;

@@ -121,6 +121,31 @@ def test_learned_form_follows_the_oracle_then_converges(c1):
     assert abs(st[-1]["energy"] - sum(ref)) < 1e-9 * abs(sum(ref))
 
 
+@pytest.mark.parametrize("p", [64, 128])
+def test_learned_form_wide_blocks_follow_the_oracle(p, c1):
+    """The learned form's column-norm epilogue of the row GEMM at p = 64 and
+    128 (multiplier held in LDS): the first iterations against the oracle's
+    within 1e-5 (FP32 network)."""
+    from paper_2007_14228_amd import Solver
+    print(f"[gpu] lp pcal p={p}", flush=True)
+    w, d, prob = c1
+    W = _weights(11)
+    norm = np.array([-1.0, -2.0, -1.0, 0.0, 1.0, 1.5, 2.0, 1.0], dtype=np.float32)
+    X0 = pcal.chol_gs(prob, wl.random_block(3, d.n, p))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=3, precond="learned",
+                                              lp_weights=(W, norm.astype(np.float64))))
+    s = Solver()
+    s.load_workload(w)
+    s.lp_set_weights(W, norm)
+    s.set_params(beta=w.beta, tol=1e-30, max_iter=3, precond="learned")
+    s.set_x0(_dev(X0), orthonormalize=False)
+    st, _, _ = s.step(4)
+    assert len(st) == len(hist) == 4
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= 1e-5 * b.kkt
+    s.close()
+
+
 def test_poisoned_network_falls_back_and_still_converges(c1):
     """Fallback forced from the host: an output bias of 3 makes every learned
     step 20x too long; the energy rises, the paper preconditioner takes over,

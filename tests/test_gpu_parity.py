@@ -257,6 +257,31 @@ def test_first_iterations_follow_the_oracle_wide_blocks(p, c1):
         assert abs(a["energy"] - b.energy) <= 1e-11 * abs(b.energy)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precond", ["none", "paper"])
+@pytest.mark.parametrize("p", [64, 128])
+def test_row_gemm_widths_follow_the_oracle(p, precond, precision, c1):
+    """p = 64 and 128, where the gradient row GEMM holds the multiplier in LDS
+    (FP64 at p = 128 in two 128-column halves, one per block), with the plain
+    gradient epilogue (no preconditioner) and the PCG-start one: the first
+    iterations against the oracle's (FP64 blocks: kkt 1e-10 and energy 1e-11
+    relative; FP32 blocks: 1e-4 and 1e-5)."""
+    w, d = c1
+    print(f"[gpu] row gemm width p={p} {precond} {precision}", flush=True)
+    prob = pcal.LinearProblem(d.row_ptr, d.col, d.H, d.B, 0.5 * d.L)
+    X0 = pcal.chol_gs(prob, wl.random_block(9, d.n, p))
+    _, hist = pcal.pcal(prob, X0, pcal.Params(beta=w.beta, tol=1e-30, max_iter=3, precond=precond))
+    s = _solver_for(w)
+    st = _run_gpu(s, X0, 3, beta=w.beta, tol=1e-30, precond=precond, pcg_iters=10, energy_every=1,
+                  precision=precision)
+    assert len(st) == len(hist) == 4
+    assert st[0]["precision"] == (1 if precision == "f32" else 0)
+    tk, te = (1e-10, 1e-11) if precision == "f64" else (1e-4, 1e-5)
+    for a, b in zip(st, hist):
+        assert abs(a["kkt"] - b.kkt) <= tk * b.kkt
+        assert abs(a["energy"] - b.energy) <= te * abs(b.energy)
+
+
 @pytest.mark.parametrize("mode", ["gather", "halo"])
 @pytest.mark.parametrize("p", [40, 130, 260, 512])
 def test_fp32_iterations_stay_close_to_the_oracle(p, mode, c1):
