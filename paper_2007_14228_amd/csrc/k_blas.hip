@@ -599,8 +599,8 @@ void k_rowgemm_mfma(int64_t n, int p, int N, const T *__restrict__ A, const T *_
 // wave after each tile and kept per wave in LDS, the residual sum per
 // thread in LDS, so neither holds registers through the MFMAs.
 // With two halves, blocks b and b + 8 (one XCD) take the two halves of the
-// same row tiles in the same order, so the second read of A and HX mostly
-// hits that XCD's L2.  The K order inside one MFMA is permuted (any order
+// same row tiles in the same order; the counters still show A and HX fetched
+// from beyond L2 once per half.  The K order inside one MFMA is permuted (any order
 // of the 4 k values of an instruction gives the same sum up to rounding).
 // LDS layout of the staged multiplier: element (k, c) at
 // (k / 4) KS + (k % 4) TCB + c, with the k/4 stride padded by 16 values so
