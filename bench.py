@@ -67,8 +67,8 @@ def parse():
     return ap.parse_args()
 
 
-P_STUDY_TIMERS = ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_r", "pcg_dx", "bbdot", "density",
-                  "poisson", "assemble_h", "mlp", "graph", "host")
+P_STUDY_TIMERS = ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_r", "pcg_dx", "pcg_sum", "bbdot",
+                  "density", "poisson", "assemble_h", "mlp", "graph", "host")
 
 
 def p_study(torch, a, s, w, params, steps=3, warmup=2):

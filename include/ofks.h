@@ -20,7 +20,11 @@
  *    iteration's state in set_x0 and, lazily, in the first steps (the rest
  *    of the FP64 blocks, the precision switch, SCF and graph-form arrays),
  *    all freed in ofks_destroy.  With a caller workspace (ofks_set_workspace)
- *    the iteration's state is carved from it instead.
+ *    the iteration's state is carved from it instead.  Without one, the
+ *    paper preconditioner also takes m - 1 scratch blocks for its inner
+ *    directions when free device memory stays above a quarter of the device
+ *    after the allocation (same results; skipped otherwise, never an
+ *    error); they are released with the iterate.
  *  - Blocks X (n x p) are row-major: the p values of one DOF are contiguous.
  *    n counts interior (non-Dirichlet) nodes, numbered in node order.
  *  - CSR matrices: row_ptr int64[n+1], col int32[nnz], columns sorted

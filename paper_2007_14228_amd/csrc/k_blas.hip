@@ -112,6 +112,12 @@ __global__ __launch_bounds__(256) void k_colsum(int64_t nb, int64_t m_total,
 // ---------------------------------------------------------------------------
 enum { EPI_PLAIN = 0, EPI_GRAD = 1, EPI_GRAD_PCG = 2, EPI_GRAD_NORM = 3 };
 
+// the directions of the inner CG's history form (k_pcg_sum), by value
+constexpr int PCG_DIRS_MAX = 16;
+struct PcgDirs {
+    const void *d[PCG_DIRS_MAX];
+};
+
 struct GradArgs {
     const void *HX;       // n x p, unnormalized (scaled by dinv here)
     void *P;              // out: gradient (no CG) / identity-branch columns
@@ -898,6 +904,84 @@ __global__ __launch_bounds__(256) void k_pcg_dx(int64_t n, int p, int lpr_log2, 
     }
 }
 
+// History form of the inner CG (memory permitting): each direction gets a
+// block of its own, so no pass reads and rewrites x; P = sum_j alpha_j d_j is
+// formed once after the last iteration (the same fmas, in the same order, as
+// the running update x += alpha_j d_j of k_pcg_dx, so the same bits).
+//   k_pcg_dnext  Dn = J r + beta D on active columns          (reads r, D; writes Dn)
+//   k_pcg_sum    X = sum_j alpha_j D_j on active columns      (reads the m D_j; writes X)
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_pcg_dnext(int64_t n, int p, int lpr_log2, const T *__restrict__ beta,
+                                                  const uint8_t *__restrict__ active,
+                                                  const double *__restrict__ lhd, const double *__restrict__ bd,
+                                                  const T *__restrict__ lam, const T *__restrict__ R,
+                                                  const T *__restrict__ D, T *__restrict__ Dn) {
+    const int lpr = 1 << lpr_log2;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lpr_log2;
+    const int lane = threadIdx.x & (lpr - 1);
+    if (row >= n) return;
+    const T ld = (T)lhd[row], bdv = (T)bd[row];
+    for (int c0 = lane * V; c0 < p; c0 += lpr * V) {
+        bool on[V], any = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            on[v] = active[c0 + v] != 0;
+            any |= on[v];
+        }
+        if (!any) continue;
+        T d[V], r[V];
+        load_vec<T, V>(D + row * p + c0, d);
+        load_vec<T, V>(R + row * p + c0, r);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (on[v]) d[v] = fma(beta[c0 + v], d[v], r[v] / (ld - lam[c0 + v] * bdv));
+        store_vec<T, V>(Dn + row * p + c0, d);
+    }
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_pcg_sum(int64_t n, int p, int lpr_log2, int m, const T *__restrict__ alpha,
+                                                const uint8_t *__restrict__ active, PcgDirs dirs,
+                                                T *__restrict__ X) {
+    const int lpr = 1 << lpr_log2;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lpr_log2;
+    const int lane = threadIdx.x & (lpr - 1);
+    if (row >= n) return;
+    for (int c0 = lane * V; c0 < p; c0 += lpr * V) {
+        bool on[V], all = true, any = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            on[v] = active[c0 + v] != 0;
+            all &= on[v];
+            any |= on[v];
+        }
+        if (!any) continue;
+        T x[V];
+        if (all) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) x[v] = T(0);
+        } else {
+            load_vec<T, V>(X + row * p + c0, x);
+        }
+        // directions in groups of 8, each group's loads in flight together
+        for (int j0 = 0; j0 < m; j0 += 8) {
+            T d[8][V];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u < m) load_vec<T, V>((const T *)dirs.d[j0 + u] + row * p + c0, d[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (j0 + u >= m) break;
+                const T *al = alpha + (int64_t)(j0 + u) * p + c0;
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (on[v]) x[v] = j0 + u == 0 ? al[v] * d[u][v] : fma(al[v], d[u][v], x[v]);
+            }
+        }
+        store_vec<T, V>(X + row * p + c0, x);
+    }
+}
+
 // alpha_c = rz_c / dq_c (0 when dq_c <= 0);  beta_c = rz_new_c / rz_c (0 when rz_c <= 0).
 template <typename T>
 __global__ void k_pcg_alpha(int p, const double *__restrict__ dq, const double *__restrict__ rz,
@@ -1348,6 +1432,31 @@ hipError_t launch_pcg_dx(hipStream_t s, int64_t n, int p, int first, int dir, co
 }
 
 template <typename T>
+hipError_t launch_pcg_dnext(hipStream_t s, int64_t n, int p, const T *beta, const uint8_t *active,
+                            const double *lhd, const double *bd, const T *lam, const T *R, const T *D, T *Dn) {
+    const int v = vwidth<T>(p);
+    const int l2 = lpr_l2(p, v);
+    const unsigned grid = (unsigned)(((n << l2) + 255) / 256);
+    if (v == 1) hipLaunchKernelGGL((k_pcg_dnext<T, 1>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D, Dn);
+    else if (v == 2) hipLaunchKernelGGL((k_pcg_dnext<T, 2>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D, Dn);
+    else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_pcg_dnext<T, 4>), dim3(grid), dim3(256), 0, s, n, p, l2, beta, active, lhd, bd, lam, R, D, Dn);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_sum(hipStream_t s, int64_t n, int p, int m, const T *alpha, const uint8_t *active,
+                          const PcgDirs &dirs, T *X) {
+    if (m < 1 || m > PCG_DIRS_MAX) return hipErrorInvalidValue;
+    const int v = vwidth<T>(p);
+    const int l2 = lpr_l2(p, v);
+    const unsigned grid = (unsigned)(((n << l2) + 255) / 256);
+    if (v == 1) hipLaunchKernelGGL((k_pcg_sum<T, 1>), dim3(grid), dim3(256), 0, s, n, p, l2, m, alpha, active, dirs, X);
+    else if (v == 2) hipLaunchKernelGGL((k_pcg_sum<T, 2>), dim3(grid), dim3(256), 0, s, n, p, l2, m, alpha, active, dirs, X);
+    else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_pcg_sum<T, 4>), dim3(grid), dim3(256), 0, s, n, p, l2, m, alpha, active, dirs, X);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_update_b(hipStream_t s, int64_t n, int p, const T *dinv, T eta, const T *P, T *Xt,
                            T *Xp) {
     const int v = vwidth<T>(p);
@@ -1404,6 +1513,8 @@ template hipError_t launch_pcg_init<float>(hipStream_t, int, int64_t, int, const
     template hipError_t launch_bbdot<T>(hipStream_t, int, int64_t, int, const T *, const T *, const T *, const T *, const T *, double *); \
     template hipError_t launch_pcg_dx<T>(hipStream_t, int64_t, int, int, int, const T *, const T *, const uint8_t *, const double *, const double *, const T *, const T *, T *, T *); \
     template hipError_t launch_update_b<T>(hipStream_t, int64_t, int, const T *, T, const T *, T *, T *); \
+    template hipError_t launch_pcg_dnext<T>(hipStream_t, int64_t, int, const T *, const uint8_t *, const double *, const double *, const T *, const T *, const T *, T *); \
+    template hipError_t launch_pcg_sum<T>(hipStream_t, int64_t, int, int, const T *, const uint8_t *, const PcgDirs &, T *); \
     template hipError_t launch_pcg_scalars<T>(hipStream_t, int, int, const double *, double *, T *);
 OFKS_INST(double)
 OFKS_INST(float)

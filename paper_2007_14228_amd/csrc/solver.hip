@@ -75,6 +75,10 @@ int halo_max_row_entries();
 int halo_pad_stride();
 int halo_row_ptr_stride();
 // (k_blas.hip)
+constexpr int PCG_DIRS_MAX = 16;
+struct PcgDirs {
+    const void *d[PCG_DIRS_MAX];
+};
 struct GradArgs {
     const void *HX;
     void *P;
@@ -115,6 +119,11 @@ hipError_t launch_pcg_dx(hipStream_t, int64_t, int, int, int, const T *, const T
                          const double *, const T *, const T *, T *, T *);
 template <typename T>
 hipError_t launch_update_b(hipStream_t, int64_t, int, const T *, T, const T *, T *, T *);
+template <typename T>
+hipError_t launch_pcg_dnext(hipStream_t, int64_t, int, const T *, const uint8_t *, const double *, const double *,
+                            const T *, const T *, const T *, T *);
+template <typename T>
+hipError_t launch_pcg_sum(hipStream_t, int64_t, int, int, const T *, const uint8_t *, const PcgDirs &, T *);
 template <typename T>
 hipError_t launch_pcg_scalars(hipStream_t, int, int, const double *, double *, T *);
 template <typename S, typename D>
@@ -298,6 +307,13 @@ struct ofks_ctx {
     int lp_objective = 0;        // 0: Euclidean imitation of T^-1 g, 1: energy-norm imitation
     void *lp_u = nullptr;        // T (J G) for the energy-norm samples
     size_t lp_u_bytes = 0;
+    // inner CG, history form: directions 1 .. m-1 (direction 0 is the D
+    // block) and the m x p step lengths; library memory, taken only while
+    // free memory allows (pcg_history)
+    void *pcg_dh = nullptr;
+    size_t pcg_dh_bytes = 0;
+    void *pcg_ah = nullptr;
+    size_t pcg_ah_bytes = 0;
 
     double *scratch_dev = nullptr;   // this device's copy of `scratch` (ofks_gram_noalloc)
     double poisson_tol_now = 0.0;    // > 0: the Hartree CG tolerance of the current iteration
@@ -829,6 +845,62 @@ double bb_eta(int rule, int k, double sy, double yy, double ss, double eta_prev,
 // ---------------------------------------------------------------------------
 // one PCAL iteration
 // ---------------------------------------------------------------------------
+// (-DOFKS_PCG_HISTORY=0 keeps the running update of x everywhere)
+#ifndef OFKS_PCG_HISTORY
+#define OFKS_PCG_HISTORY 1
+#endif
+// Inner CG, history form: each direction gets a block of its own and
+// P = sum_j alpha_j d_j is formed once at the end, which saves the read and
+// write of x in every inner iteration (m - 1 extra blocks: 18 GB for FP64
+// at n = 2e6, p = 128, m = 10).  Taken only without a caller workspace and
+// while free device memory stays above a quarter of the device (or four
+// blocks) after the allocation; otherwise pcg_run keeps x up to date as it
+// goes.  The two forms give the same bits.
+void free_pcg_history(ofks_ctx *c) {
+    if (c->pcg_dh || c->pcg_ah) (void)hipStreamSynchronize(c->stream);   // queued work may still use them
+    dfree(c, c->pcg_dh);
+    dfree(c, c->pcg_ah);
+    c->pcg_dh_bytes = c->pcg_ah_bytes = 0;
+}
+
+template <typename T> bool pcg_history(ofks_ctx *c, int m, int64_t n, int p) {
+    if (c->ws_base || m < 2 || m > PCG_DIRS_MAX) return false;
+    const size_t blk = (size_t)n * p * sizeof(T);
+    const size_t need = blk * (size_t)(m - 1), need_a = (size_t)m * p * sizeof(T);
+    if (c->pcg_dh && c->pcg_dh_bytes == need && c->pcg_ah_bytes >= need_a) return true;
+    free_pcg_history(c);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const size_t reserve = std::max(tot / 4, 4 * blk);
+    if (fr < need + need_a + reserve) return false;
+    void *dh = nullptr, *ah = nullptr;
+    if (hipMalloc(&dh, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (hipMalloc(&ah, need_a) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(dh);
+        return false;
+    }
+    c->allocs.push_back(dh);
+    c->allocs.push_back(ah);
+    // defined contents in the columns no iteration writes (inactive ones)
+    if (hipMemsetAsync(dh, 0, need, c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        free_pcg_history(c);
+        return false;
+    }
+    c->pcg_dh = dh;
+    c->pcg_dh_bytes = need;
+    c->pcg_ah = ah;
+    c->pcg_ah_bytes = need_a;
+    return true;
+}
+
 // P = T^-1 G columnwise by m Jacobi-PCG iterations from zero (eq. precondition-T).
 // On entry R = G and D = J G on active columns, rz = <G, J G>; X holds the
 // identity-branch columns already.  Q is scratch for the operator output.
@@ -836,6 +908,34 @@ template <typename T>
 int pcg_run(ofks_ctx *c, int m, int64_t n, int p, const uint8_t *act, const T *lam, const void *lb, T *D, T *Q, T *X,
             T *R, T *alpha, T *beta, double *rz) {
     CHK(ensure_part(c, (size_t)c->grid * p));
+    if (OFKS_PCG_HISTORY && pcg_history<T>(c, m, n, p)) {
+        PcgDirs dirs{};
+        T *dh = (T *)c->pcg_dh;
+        for (int j = 0; j < m; ++j) dirs.d[j] = j == 0 ? (const void *)D : (const void *)(dh + (size_t)(j - 1) * n * p);
+        T *ah = (T *)c->pcg_ah;
+        for (int it = 0; it < m; ++it) {
+            T *Dj = (T *)dirs.d[it];
+            T *al = ah + (size_t)it * p;
+            int used = 0;
+            CHK(spmm_shift<T>(c, p, lb, lam, act, Dj, Q, &used));
+            HIPCHK(launch_colsum(c->stream, used, p, c->part, c->red));
+            HIPCHK(launch_pcg_scalars<T>(c->stream, p, 0, c->red, rz, al));
+            if (it + 1 < m) {
+                {
+                    Scope sc(c, "pcg_r");
+                    HIPCHK(launch_pcg_r<T>(c->stream, c->grid, n, p, al, act, c->lhd, c->bd, lam, Q, R, c->part));
+                }
+                HIPCHK(launch_colsum(c->stream, c->grid, p, c->part, c->red));
+                HIPCHK(launch_pcg_scalars<T>(c->stream, p, 1, c->red, rz, beta));
+                Scope sc(c, "pcg_dx");
+                HIPCHK(launch_pcg_dnext<T>(c->stream, n, p, beta, act, c->lhd, c->bd, lam, R, Dj,
+                                           (T *)dirs.d[it + 1]));
+            }
+        }
+        Scope sc(c, "pcg_sum");
+        HIPCHK(launch_pcg_sum<T>(c->stream, n, p, m, ah, act, dirs, X));
+        return OFKS_OK;
+    }
     for (int it = 0; it < m; ++it) {
         int used = 0;
         CHK(spmm_shift<T>(c, p, lb, lam, act, D, Q, &used));
@@ -1220,6 +1320,7 @@ int promote_to_f64_impl(ofks_ctx *c) {
     if (c->ws_base && c->ws_carve && ws_block_set(c->n, c->p, sizeof(double), 8) > c->ws_f64_cap)
         return fail(c, OFKS_ECAPACITY, "workspace: no room kept for the FP64 blocks (sized with refine_tol = 0)");
     CHK(sync(c));
+    free_pcg_history(c);   // FP32 directions; the FP64 set comes first
     dfree(c, F.P);
     dfree(c, F.HX);
     dfree(c, F.BX);
@@ -1298,6 +1399,7 @@ int complete_blocks(ofks_ctx *c) {
 // Releases every piece of device state a workspace may hold (those inside
 // the workspace are only forgotten); the iterate is gone afterwards.
 void release_state(ofks_ctx *c) {
+    free_pcg_history(c);
     free_blocks<double>(c);
     free_blocks<float>(c);
     dfree(c, c->active);
