@@ -932,10 +932,36 @@ __global__ __launch_bounds__(256) void k_pcg_dnext(int64_t n, int p, int lpr_log
         T d[V], r[V];
         load_vec<T, V>(D + row * p + c0, d);
         load_vec<T, V>(R + row * p + c0, r);
+        T bt[V], lm[V];
+        load_vec<T, V>(beta + c0, bt);
+        load_vec<T, V>(lam + c0, lm);
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-            if (on[v]) d[v] = fma(beta[c0 + v], d[v], r[v] / (ld - lam[c0 + v] * bdv));
+        for (int v = 0; v < V; ++v) {   // a select, not a branch, per column
+            const T nd = fma(bt[v], d[v], r[v] / (ld - lm[v] * bdv));
+            d[v] = on[v] ? nd : d[v];
+        }
         store_vec<T, V>(Dn + row * p + c0, d);
+    }
+}
+
+// G directions j0 .. j0 + G - 1 of one lane's V columns: all G loads issued
+// before the first fma (no branch between them), then the fmas in order of j
+template <int G, typename T, int V>
+__device__ __forceinline__ void pcg_sum_group(int j0, int64_t off, int p, int c0, const T *__restrict__ alpha,
+                                              const PcgDirs &dirs, const bool (&on)[V], T (&x)[V]) {
+    T d[G][V];
+#pragma unroll
+    for (int u = 0; u < G; ++u) load_vec<T, V>((const T *)dirs.d[j0 + u] + off, d[u]);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        T al[V];
+        load_vec<T, V>(alpha + (int64_t)(j0 + u) * p + c0, al);
+        const bool first = j0 + u == 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const T nv = first ? al[v] * d[u][v] : fma(al[v], d[u][v], x[v]);
+            x[v] = on[v] ? nv : x[v];
+        }
     }
 }
 
@@ -963,21 +989,13 @@ __global__ __launch_bounds__(256) void k_pcg_sum(int64_t n, int p, int lpr_log2,
         } else {
             load_vec<T, V>(X + row * p + c0, x);
         }
-        // directions in groups of 8, each group's loads in flight together
-        for (int j0 = 0; j0 < m; j0 += 8) {
-            T d[8][V];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (j0 + u < m) load_vec<T, V>((const T *)dirs.d[j0 + u] + row * p + c0, d[u]);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (j0 + u >= m) break;
-                const T *al = alpha + (int64_t)(j0 + u) * p + c0;
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-                    if (on[v]) x[v] = j0 + u == 0 ? al[v] * d[u][v] : fma(al[v], d[u][v], x[v]);
-            }
-        }
+        // the directions in groups of 8, then 4, 2, 1 (m = 10: 8 + 2)
+        const int64_t off = row * p + c0;
+        int j = 0;
+        for (; j + 8 <= m; j += 8) pcg_sum_group<8>(j, off, p, c0, alpha, dirs, on, x);
+        if (j + 4 <= m) { pcg_sum_group<4>(j, off, p, c0, alpha, dirs, on, x); j += 4; }
+        if (j + 2 <= m) { pcg_sum_group<2>(j, off, p, c0, alpha, dirs, on, x); j += 2; }
+        if (j < m) pcg_sum_group<1>(j, off, p, c0, alpha, dirs, on, x);
         store_vec<T, V>(X + row * p + c0, x);
     }
 }
