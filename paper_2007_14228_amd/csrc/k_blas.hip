@@ -837,9 +837,10 @@ __global__ __launch_bounds__(256) void k_pcg_r(int64_t n, int p, int lpr_log2, c
             load_vec<T, V>(Q + row * p + c0, q);
             load_vec<T, V>(R + row * p + c0, r);
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
+            for (int v = 0; v < V; ++v) {   // selects, not branches, per column
                 r[v] = fma(-al[ch][v], q[v], r[v]);
-                if (on[ch][v]) dot[ch][v] += (double)r[v] * (double)(r[v] / (ld - lm[ch][v] * bdv));
+                const double t = (double)r[v] * (double)(r[v] / (ld - lm[ch][v] * bdv));
+                dot[ch][v] = on[ch][v] ? dot[ch][v] + t : dot[ch][v];
             }
             store_vec<T, V>(R + row * p + c0, r);
         }
@@ -892,12 +893,20 @@ __global__ __launch_bounds__(256) void k_pcg_dx(int64_t n, int p, int lpr_log2, 
         } else {
             load_vec<T, V>(X + row * p + c0, x);
         }
+        T a[V], bt[V], lm[V];
+        load_vec<T, V>(alpha + c0, a);
+        if (DIR) {
+            load_vec<T, V>(beta + c0, bt);
+            load_vec<T, V>(lam + c0, lm);
+        }
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            if (!on[v]) continue;
-            const T a = alpha[c0 + v];
-            x[v] = first ? a * d[v] : fma(a, d[v], x[v]);
-            if (DIR) d[v] = fma(beta[c0 + v], d[v], r[v] / (ld - lam[c0 + v] * bdv));
+        for (int v = 0; v < V; ++v) {   // selects, not branches, per column
+            const T nx = first ? a[v] * d[v] : fma(a[v], d[v], x[v]);
+            x[v] = on[v] ? nx : x[v];
+            if (DIR) {
+                const T nd = fma(bt[v], d[v], r[v] / (ld - lm[v] * bdv));
+                d[v] = on[v] ? nd : d[v];
+            }
         }
         store_vec<T, V>(X + row * p + c0, x);
         if (DIR) store_vec<T, V>(D + row * p + c0, d);
