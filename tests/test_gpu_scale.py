@@ -129,7 +129,7 @@ def test_c4_fp32_iterations(c4):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / len(st)
     timers = {k: s.timer(k) for k in ("spmm_dual", "spmm_shift", "gram", "update_a", "update_b", "pcg_r", "pcg_dx",
-                                      "bbdot")}
+                                      "pcg_sum", "bbdot")}
     print(f"[gpu] c4: {dt * 1e3:.1f} ms/iteration; " +
           " ".join(f"{k}={v[0] / max(v[1], 1):.3f}ms" for k, v in timers.items() if v[1]), flush=True)
     print("[gpu] c4: " + "; ".join(f"k={x['k']} kkt={x['kkt']:.4e} fea={x['fea']:.2e}" for x in st), flush=True)
